@@ -1,0 +1,168 @@
+"""Benchmark of the ISRS GN pair-integral engine on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-fp64] [--grad|--no-grad]
+
+One step = one full pass of the hot path on the O-to-U system (589 x 96 GBaud,
+1260-1675 nm, 80 km SSMF, G=128, N_M=112, FP32 form): distance steps, ODE power
+profile, all 589^2 COI x interferer pair integrals, NLI/SNR/throughput reduction and,
+with --grad (default once the adjoint is built), the adjoint gradient of the throughput
+with respect to all 589 launch powers.  Inputs are seeded and synthetic and are resident
+in HBM before the timed region.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Minimal VALU issue slots per node-step for eq. (psi_fin)'s step term on gfx950 (the design doc,
+# "Roofline"): 4 transcendentals (sin, cos of the phase, sin of the sinc, exp of the power
+# term) at a quarter of the FP32 rate = 16 slots, plus 14 single-rate FP32 operations.
+SLOTS_PER_NODE_STEP = 30
+FLOP_EQ_PER_SLOT = 2            # one FMA slot = 2 FLOP at the FP32 vector peak
+PEAK_FP32_TFLOPS = 157.3        # MI355X FP32 vector (no matrix cores)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--grid", type=int, default=128)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
+    ap.add_argument("--no-fp64", action="store_true", help="skip timing the FP64 GPU form")
+    ap.add_argument("--grad", dest="grad", action="store_true", default=None)
+    ap.add_argument("--no-grad", dest="grad", action="store_false")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the pair integrals would shard by COI rows; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2401_18022_amd import binding as B
+    from paper_2401_18022_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    wl = W.config_ou(grid_s=args.grid, grid_v=args.grid)
+    n = len(wl.plan.f_hz)
+    P = torch.tensor(wl.plan.p_w, dtype=torch.float64, device="cuda")
+    nf = torch.tensor(wl.plan.nf_lin, dtype=torch.float64, device="cuda")
+
+    def make(prec):
+        e = B.Engine(wl.fibre, prec)
+        e.set_timing(True)
+        return e
+
+    eng = make(W.FP32)
+    grad = args.grad
+    if grad is None:
+        try:
+            eng.snr_grad(wl.plan, P, nf)
+            torch.cuda.synchronize()
+            grad = True
+        except B.IsrsgnError as e:
+            if e.code != B.ISRSGN_EUNSUPPORTED:
+                raise
+            grad = False
+
+    def step(e):
+        if grad:
+            return e.snr_grad(wl.plan, P, nf)
+        return e.snr(wl.plan, P, nf)
+
+    for _ in range(args.warmup):
+        step(eng)
+    torch.cuda.synchronize()
+    stages = {k: 0.0 for k in ("profile", "tiles", "reduce", "adjoint_tiles", "adjoint_rest", "total")}
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = step(eng)
+        st = eng.stage_times()          # waits for this step's last event
+        for k in stages:
+            stages[k] += st[k]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    thr = out[1].item()
+    work = eng.work_counts()
+    ms_step = 1e3 * elapsed / args.steps
+    tiles_ms = stages["tiles"] / args.steps
+    node_steps = work["node_steps"]
+    achieved = node_steps * SLOTS_PER_NODE_STEP * FLOP_EQ_PER_SLOT / (tiles_ms * 1e-3) / 1e12
+    dominant = "pair_integral_forward"
+    dom_ms = tiles_ms
+    if grad and stages["adjoint_tiles"] / args.steps > tiles_ms:
+        dominant = "pair_integral_adjoint"
+        dom_ms = stages["adjoint_tiles"] / args.steps
+
+    fp64 = None
+    if not args.no_fp64:
+        e64 = make(W.FP64)
+        step(e64)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        step(e64)
+        s64 = e64.stage_times()
+        torch.cuda.synchronize()
+        fp64 = dict(ms_per_step=1e3 * (time.perf_counter() - t1), tiles_ms=s64["tiles"],
+                    speedup_fp32_over_fp64=(1e3 * (time.perf_counter() - t1)) / ms_step)
+        e64.close()
+
+    cpu = None
+    if not args.no_cpu:
+        from oracle import oracle as orc
+        sample_coi = [n // 2]
+        o = orc.Oracle(wl.fibre, wl.plan)
+        tc = time.perf_counter()
+        o.forward(coi=sample_coi)
+        dt = time.perf_counter() - tc
+        cpu = {"value": len(sample_coi) * n / dt, "unit": "pair-integrals/s", "cores": o.threads, "kind": "oracle",
+               "sample": f"FP64 oracle, forward pair integrals of COI {sample_coi[0]} x all {n} interferers "
+                         f"(G={args.grid}, N_M={wl.fibre.n_steps}), {dt:.1f} s on {o.threads} threads; "
+                         f"no profile adjoint"}
+
+    res = {
+        "metric": "NLI pair-integrals/s + 589-ch SNR+gradient wall time, FP32 vs FP64 form, 1 GPU",
+        "value": n * n / (ms_step * 1e-3),
+        "unit": "pair-integrals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 integrand, f64 phase/accumulation",
+        "data": "synthetic (seeded channel plan and fibre tables shaped like the paper's O-to-U system)",
+        "config": {"workload": f"O-to-U 589x96GBaud 100GHz 1260-1675nm, 80 km SSMF, ODE ISRS profile, "
+                               f"G={args.grid}x{args.grid}, N_M={wl.fibre.n_steps}, FP32 form, "
+                               + ("SNR + adjoint gradient" if grad else "SNR (forward) only"),
+                   "pairs_per_step": n * n, "grad": bool(grad)},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None, "kernel": dominant,
+                     "kernel_ms": dom_ms, "node_steps_per_launch": node_steps,
+                     "slots_per_node_step": SLOTS_PER_NODE_STEP},
+        "cpu_baseline": cpu,
+        "stages_ms": {k: v / args.steps for k, v in stages.items()},
+        "node_steps_per_s": node_steps / (tiles_ms * 1e-3),
+        "throughput_tbps": thr / 1e12,
+        "fp64_form": fp64,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

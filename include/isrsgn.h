@@ -1,0 +1,157 @@
+/*
+ * isrsgn.h -- C ABI of the MI355X ISRS Gaussian-noise numerical-integral engine.
+ *
+ * The library evaluates the nonlinear-interference (NLI) model of
+ * Jarmolovicius et al., "Optimising O-to-U Band Transmission Using Fast ISRS
+ * Gaussian Noise Numerical Integral Model" (arXiv:2401.18022):
+ *
+ *   - the NLI PSD at a channel of interest (COI), eq. (new_gn_model), solved as
+ *     in App. A: distance-step sum eq. (slow_vary), power-profile term eq. (pk),
+ *     phase mismatch with beta2..beta4 eq. (phi), quadrants eqs. (q1a)-(q4d) and
+ *     hyperbolic coordinates eqs. (q1)-(q4), assembled by eqs. (gain_fin)/(psi_fin);
+ *   - the link cost eq. (loss) and the throughput C = 2 B_ch (-L) of Sec. IV;
+ *   - its gradient with respect to every launch power (hand-written adjoint).
+ *
+ * Discretisation (the paper leaves node placement open; these definitions are
+ * part of the interface):
+ *   * tile (i,k) is the part of the (f1, f2) plane, offsets x = f1 - f_i and
+ *     y = f2 - f_i within the band, where f1 + f2 - f_i falls in channel k;
+ *     tile(i,k) = sum over parts Q1 (x,y>0, folded about x=y), Q3 (x,y<0, folded)
+ *     and Q4 (x>0>y, standing for Q2 too) of a Riemann sum in s = ln|x y| and
+ *     v = ln sqrt|x/y|: grid_s midpoints over [ln U - s_decades ln 10, ln U]
+ *     (U = sup|x y| over the part) and grid_v midpoints between the exact
+ *     per-row v limits; node weight 2 e^s ds dv (unit Jacobian);
+ *   * distance steps: n_steps steps with equal power decrement under the mean
+ *     loss of the occupied channels, the power term evaluated at the midpoints;
+ *   * ln rho(z, f) is interpolated linearly in f between channel centres;
+ *   * P_NLI,i = 16/27 gamma_i^2 R_i sum_k tile(i,k); eta_i = P_NLI,i / P_i^3;
+ *     P_ASE,i = NF_i h f_i R_i / rho(L, f_i);  SNR_i = P_i / (P_NLI,i + P_ASE,i)
+ *     (combined with a transceiver SNR as 1/(1/SNR + 1/SNR_trx) when given);
+ *     T = sum over P_i > 0 of 2 R_i log2(1 + SNR_i).
+ *
+ * Conventions: SI units everywhere (Hz, W, m, s).  All arrays are FP64.
+ * Arrays named *_dev are device pointers owned by the caller (e.g. torch
+ * tensors); everything else is host memory, read during the call only.
+ * Work is enqueued on the given HIP stream (NULL = the default stream) and the
+ * calls return without synchronising.  A handle must not be used by two host
+ * threads at once.  Every call returns ISRSGN_OK or a negative error code and
+ * leaves a message for isrsgn_last_error(); on error nothing is written to the
+ * outputs.
+ */
+#ifndef ISRSGN_H
+#define ISRSGN_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct isrsgn_fibre isrsgn_fibre; /* opaque: fibre tables, device workspace, caches */
+
+enum {
+  ISRSGN_OK = 0,
+  ISRSGN_EINVAL = -1,      /* invalid argument (message says which) */
+  ISRSGN_ENOMEM = -2,      /* device allocation failed; the handle stays usable */
+  ISRSGN_EDEVICE = -3,     /* HIP runtime error (message carries the HIP error string) */
+  ISRSGN_EUNSUPPORTED = -4 /* a combination this build does not provide */
+};
+
+enum { ISRSGN_FP32 = 0, ISRSGN_FP64 = 1 };
+enum { ISRSGN_PROFILE_CLOSED_FORM = 0, ISRSGN_PROFILE_ODE = 1 };
+
+/* Fibre and discretisation (Sec. II, Table I, App. A).  Deep-copied by
+ * isrsgn_setup_fibre; the caller may free it on return. */
+typedef struct {
+  double span_m;            /* span length L */
+  double f_ref_hz;          /* reference frequency of the dispersion Taylor series (w_i = f_i - f_ref) */
+  double beta2, beta3, beta4; /* s^2/m, s^3/m, s^4/m at f_ref; used when disp_from_d == 0 */
+  int disp_from_d;          /* 1: betas from D, S, dS/dlambda at lambda = c/f_ref, eqs. (d)-(d_curve) */
+  double d_s_per_m2, s_s_per_m3, sdot_s_per_m4;
+  int n_tab;                /* >= 1 points of loss and effective area vs frequency (ascending), */
+  const double* tab_f_hz;   /*   interpolated linearly in f and held constant beyond the ends    */
+  const double* alpha_per_m;
+  const double* aeff_m2;
+  double n2_m2_per_w;       /* gamma(f) = 2 pi n2 f / (c A_eff(f)), eq. (gamma) */
+  double gamma_const_per_w_m; /* > 0 overrides gamma(f) with a constant */
+  double cr_per_w_m_hz;     /* Raman gain slope C_r at aeff_ref_m2; channel k uses C_r A_ref / A_eff(f_k) */
+  double aeff_ref_m2;
+  double raman_cutoff_hz;   /* triangular gain: zero beyond this offset; <= 0: linear over the band */
+  int profile;              /* ISRSGN_PROFILE_CLOSED_FORM (needs n_tab == 1) or ISRSGN_PROFILE_ODE */
+  int photon_ratio;         /* ODE: the higher-frequency channel loses f_k/f_j times the power gained */
+  int n_steps;              /* distance steps N_M, 1..4096 */
+  int grid_s, grid_v;       /* nodes per part: grid_s (2..1024) rows x grid_v (2..65536) per row */
+  double s_decades;         /* depth of the ln|xy| window below sup|xy|, > 0 (14 is ample) */
+  int ode_sub;              /* ODE: RK4 sub-steps per half distance step, 1..64 */
+  int precision;            /* ISRSGN_FP32 (FP32 integrand, FP64 phase and sums) or ISRSGN_FP64 */
+} isrsgn_fibre_desc;
+
+/* One or more channel plans, concatenated CSR-style (host memory).
+ * Plan b owns channels [ch_offsets[b], ch_offsets[b+1]); each plan is sorted by
+ * frequency with non-overlapping rectangular channels (f_{k+1} - f_k >= (R_k + R_{k+1})/2),
+ * 1..1024 channels.  Device copies are cached by content. */
+typedef struct {
+  int n_batch;
+  const int* ch_offsets;    /* n_batch + 1 entries, ch_offsets[0] == 0 */
+  const double* f_hz;       /* channel centres */
+  const double* rs_hz;      /* symbol rates = rectangular PSD widths (Sec. III) */
+} isrsgn_plan;
+
+/* Creates a handle.  Validates desc (EINVAL), converts the dispersion, copies the
+ * tables.  *out is set only on success; release it with isrsgn_destroy. */
+int isrsgn_setup_fibre(const isrsgn_fibre_desc* desc, isrsgn_fibre** out);
+
+/* NLI of every channel of every plan: eq. (gain_fin) times R_i.
+ *   P_w_dev[n_ch_total]     launch powers (>= 0; 0 marks an empty channel, the set A of eq. loss)
+ *   eta_dev[n_ch_total]     eta_i = P_NLI,i / P_i^3 (NaN where P_i == 0)
+ *   pnli_w_dev[n_ch_total]  P_NLI,i in W (may be NULL)
+ *   tile_dev_or_null        per plan an N_b x N_b row-major block [i][k] of tile integrals
+ *                           (W^3/Hz^3 * Hz^2 * m^2), blocks concatenated in plan order; may be NULL */
+int isrsgn_eta(isrsgn_fibre* h, const isrsgn_plan* plan, const double* P_w_dev, double* eta_dev,
+               double* pnli_w_dev, double* tile_dev_or_null, void* hip_stream);
+
+/* SNR per channel and throughput per plan (eq. loss, Sec. IV).
+ *   nf_lin_dev[n_ch_total]  amplifier noise figure (linear)
+ *   snr_trx_lin             transceiver back-to-back SNR (linear); 0 = ideal transceiver
+ *   snr_dev[n_ch_total]     linear SNR (0 where P_i == 0)
+ *   thr_bps_dev[n_batch]    throughput in bit/s */
+int isrsgn_snr(isrsgn_fibre* h, const isrsgn_plan* plan, const double* P_w_dev, const double* nf_lin_dev,
+               double snr_trx_lin, double* snr_dev, double* thr_bps_dev, void* hip_stream);
+
+/* isrsgn_snr plus the exact gradient of each plan's throughput with respect to every
+ * launch power, through the PSD products and the power profile (adjoint method).
+ *   dthr_dP_dev[n_ch_total] d thr_b / d P_k in bit/s/W for k in plan b */
+int isrsgn_snr_grad(isrsgn_fibre* h, const isrsgn_plan* plan, const double* P_w_dev, const double* nf_lin_dev,
+                    double snr_trx_lin, double* snr_dev, double* thr_bps_dev, double* dthr_dP_dev,
+                    void* hip_stream);
+
+/* The distance steps and the power profile on their own (App. A, eq. pk):
+ *   z_mid_dev[n_batch * n_steps], dz_dev[n_batch * n_steps]  step midpoints and widths per plan
+ *   ell_dev   per plan an n_steps x N_b row-major block of ln rho(z_m, f_c)
+ *   ell_L_dev[n_ch_total]     ln rho(L, f_c)
+ * Any output may be NULL. */
+int isrsgn_profile(isrsgn_fibre* h, const isrsgn_plan* plan, const double* P_w_dev, double* z_mid_dev,
+                   double* dz_dev, double* ell_dev, double* ell_L_dev, void* hip_stream);
+
+/* Stage timers.  When enabled, every call records HIP events around its stages on
+ * its stream.  isrsgn_stage_times waits for the last call and writes milliseconds
+ * for: [0] steps+profile, [1] pair integrals (forward tile kernel), [2] reduction,
+ * [3] adjoint tile kernel, [4] profile adjoint + gradient assembly, [5] whole call;
+ * stages that did not run read 0.  n is the capacity of ms_out (up to 6). */
+int isrsgn_set_timing(isrsgn_fibre* h, int enabled);
+int isrsgn_stage_times(isrsgn_fibre* h, double* ms_out, int n);
+
+/* Work done by the last forward pair-integral launch on the most recently used plan
+ * (waits for it): [0] nodes evaluated (nodes on the channel support of non-empty rows),
+ * [1] node-steps = nodes * n_steps, [2] tiles.  n is the capacity of out (up to 3). */
+int isrsgn_work_counts(isrsgn_fibre* h, double* out, int n);
+
+/* Frees the handle and its device memory (waits for its outstanding work).  NULL is allowed. */
+void isrsgn_destroy(isrsgn_fibre* h);
+
+/* Message of the last failed call on this thread ("" if none). Valid until the next call. */
+const char* isrsgn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ISRSGN_H */

@@ -1,0 +1,451 @@
+// Host runtime of libisrsgn.so: the C ABI of include/isrsgn.h -- argument validation,
+// handle and device-memory ownership, the plan cache, and the order of kernel launches.
+#include "isrsgn.h"
+#include "isrsgn_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+using namespace isrsgn;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(ISRSGN_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr double kC = 299792458.0;
+constexpr double kPi = 3.14159265358979323846;
+
+// Device allocation; ISRSGN_FAIL_ALLOC=1 in the environment makes it fail (tests of ENOMEM).
+bool dev_alloc(void** p, size_t bytes) {
+  *p = nullptr;
+  const char* inj = std::getenv("ISRSGN_FAIL_ALLOC");
+  if (inj && inj[0] == '1') return false;
+  if (bytes == 0) bytes = 16;
+  return hipMalloc(p, bytes) == hipSuccess;
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf() { if (p) (void)hipFree(p); }
+  bool ensure(size_t n) {
+    if (n <= bytes && p) return true;
+    if (p) { (void)hipFree(p); p = nullptr; bytes = 0; }
+    if (!dev_alloc(&p, n)) { p = nullptr; return false; }
+    bytes = n;
+    return true;
+  }
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+uint64_t fnv1a(const void* data, size_t n, uint64_t h) {
+  const unsigned char* c = static_cast<const unsigned char*>(data);
+  for (size_t i = 0; i < n; ++i) { h ^= c[i]; h *= 1099511628211ull; }
+  return h;
+}
+
+// A validated channel plan resident on the device, with its workspace.
+struct PlanEntry {
+  uint64_t key = 0;
+  std::vector<int> off;
+  std::vector<double> f, R;
+  int n_batch = 0, n_total = 0, nmax = 0;
+  int64_t n_tiles = 0;
+  DevBuf d_off, d_toff, d_f, d_R, d_alpha, d_aeff, d_gamma, d_cr;
+  // workspace
+  DevBuf abar, zm, dz, hdz32, ell64, lt32, ellL, tiles, pnli, snr, counter;
+  DevBuf states, state_off, lam, gG, gL, gLL, gP;
+  bool grad_ready = false;
+  PlanView view() const {
+    PlanView v;
+    v.n_batch = n_batch;
+    v.n_total = n_total;
+    v.n_tiles = n_tiles;
+    v.off = d_off.as<int>();
+    v.toff = d_toff.as<int64_t>();
+    v.f = d_f.as<double>();
+    v.R = d_R.as<double>();
+    v.alpha = d_alpha.as<double>();
+    v.aeff = d_aeff.as<double>();
+    v.gamma = d_gamma.as<double>();
+    v.cr = d_cr.as<double>();
+    return v;
+  }
+  Work work() const {
+    Work w{};
+    w.abar = abar.as<double>();
+    w.zm = zm.as<double>();
+    w.dz = dz.as<double>();
+    w.hdz32 = hdz32.as<float>();
+    w.ell64 = ell64.as<double>();
+    w.lt32 = lt32.as<float2>();
+    w.ellL = ellL.as<double>();
+    w.tiles = tiles.as<double>();
+    w.pnli = pnli.as<double>();
+    w.snr = snr.as<double>();
+    w.counter = counter.as<unsigned int>();
+    w.nodes = reinterpret_cast<unsigned long long*>(counter.as<char>() + 32);
+    w.states = states.as<double>();
+    w.state_off = state_off.as<int64_t>();
+    w.lam = lam.as<double>();
+    w.gG = gG.as<double>();
+    w.gL = gL.as<double>();
+    w.gLL = gLL.as<double>();
+    w.gP = gP.as<double>();
+    return w;
+  }
+};
+
+}  // namespace
+
+struct isrsgn_fibre {
+  isrsgn_fibre_desc desc{};
+  std::vector<double> tab_f, tab_alpha, tab_aeff;
+  DevBuf d_tab_f, d_tab_alpha, d_tab_aeff;
+  FibreParams fp{};
+  int device = 0, n_cu = 0;
+  std::vector<std::unique_ptr<PlanEntry>> plans;  // most recent first
+  bool timing = false;
+  hipEvent_t ev[7] = {};
+  bool ev_used[7] = {};
+  bool ev_ready = false;
+};
+
+namespace {
+
+bool is_fin(double x) { return std::isfinite(x); }
+
+int validate_desc(const isrsgn_fibre_desc* d) {
+  if (!d) return fail(ISRSGN_EINVAL, "desc is NULL");
+  if (!(d->span_m > 0) || !is_fin(d->span_m)) return fail(ISRSGN_EINVAL, "span_m must be > 0");
+  if (!(d->f_ref_hz > 0) || !is_fin(d->f_ref_hz)) return fail(ISRSGN_EINVAL, "f_ref_hz must be > 0");
+  if (d->n_tab < 1 || !d->tab_f_hz || !d->alpha_per_m || !d->aeff_m2)
+    return fail(ISRSGN_EINVAL, "need n_tab >= 1 and the three table arrays");
+  for (int q = 0; q < d->n_tab; ++q) {
+    if (!is_fin(d->tab_f_hz[q]) || !(d->alpha_per_m[q] >= 0) || !(d->aeff_m2[q] > 0))
+      return fail(ISRSGN_EINVAL, "table entry %d: need finite f, alpha >= 0, aeff > 0", q);
+    if (q > 0 && !(d->tab_f_hz[q] > d->tab_f_hz[q - 1])) return fail(ISRSGN_EINVAL, "tab_f_hz must ascend");
+  }
+  if (d->profile != ISRSGN_PROFILE_CLOSED_FORM && d->profile != ISRSGN_PROFILE_ODE)
+    return fail(ISRSGN_EUNSUPPORTED, "profile %d is not provided", d->profile);
+  if (d->profile == ISRSGN_PROFILE_CLOSED_FORM && d->n_tab != 1)
+    return fail(ISRSGN_EINVAL, "the closed-form profile needs uniform loss and area (n_tab == 1)");
+  if (d->precision != ISRSGN_FP32 && d->precision != ISRSGN_FP64)
+    return fail(ISRSGN_EUNSUPPORTED, "precision %d is not provided", d->precision);
+  if (d->n_steps < 1 || d->n_steps > 4096) return fail(ISRSGN_EINVAL, "n_steps must be in 1..4096");
+  if (d->grid_s < 2 || d->grid_s > kMaxGridS) return fail(ISRSGN_EINVAL, "grid_s must be in 2..%d", kMaxGridS);
+  if (d->grid_v < 2 || d->grid_v > 65536) return fail(ISRSGN_EINVAL, "grid_v must be in 2..65536");
+  if (!(d->s_decades > 0) || d->s_decades > 40) return fail(ISRSGN_EINVAL, "s_decades must be in (0, 40]");
+  if (d->ode_sub < 1 || d->ode_sub > 64) return fail(ISRSGN_EINVAL, "ode_sub must be in 1..64");
+  if (!(d->cr_per_w_m_hz >= 0) || !(d->aeff_ref_m2 > 0)) return fail(ISRSGN_EINVAL, "need cr >= 0 and aeff_ref > 0");
+  if (!(d->n2_m2_per_w >= 0) || !(d->gamma_const_per_w_m >= 0)) return fail(ISRSGN_EINVAL, "need n2, gamma >= 0");
+  const double vals[] = {d->beta2, d->beta3, d->beta4, d->d_s_per_m2, d->s_s_per_m3, d->sdot_s_per_m4,
+                         d->raman_cutoff_hz};
+  for (double v : vals)
+    if (!is_fin(v)) return fail(ISRSGN_EINVAL, "dispersion and cut-off must be finite");
+  return ISRSGN_OK;
+}
+
+// Validates a plan and returns its resident copy (uploading and setting it up on a miss).
+int get_plan(isrsgn_fibre* h, const isrsgn_plan* p, hipStream_t s, PlanEntry** out) {
+  if (!p) return fail(ISRSGN_EINVAL, "plan is NULL");
+  if (p->n_batch < 1 || !p->ch_offsets || !p->f_hz || !p->rs_hz) return fail(ISRSGN_EINVAL, "plan needs n_batch >= 1 and arrays");
+  if (p->ch_offsets[0] != 0) return fail(ISRSGN_EINVAL, "ch_offsets[0] must be 0");
+  int64_t ntiles = 0;
+  int nmax = 0;
+  for (int b = 0; b < p->n_batch; ++b) {
+    const int lo = p->ch_offsets[b], hi = p->ch_offsets[b + 1], n = hi - lo;
+    if (n < 1 || n > kMaxChannels) return fail(ISRSGN_EINVAL, "plan %d has %d channels (need 1..%d)", b, n, kMaxChannels);
+    for (int c = lo; c < hi; ++c) {
+      if (!is_fin(p->f_hz[c]) || !(p->f_hz[c] > 0) || !is_fin(p->rs_hz[c]) || !(p->rs_hz[c] > 0))
+        return fail(ISRSGN_EINVAL, "channel %d: need finite f > 0 and symbol rate > 0", c);
+      if (c > lo && p->f_hz[c] - p->f_hz[c - 1] < 0.5 * (p->rs_hz[c] + p->rs_hz[c - 1]))
+        return fail(ISRSGN_EINVAL, "plan %d: channels %d and %d are unsorted or overlap", b, c - 1 - lo, c - lo);
+    }
+    ntiles += (int64_t)n * n;
+    if (n > nmax) nmax = n;
+  }
+  if (ntiles >= (int64_t)1 << 31) return fail(ISRSGN_EINVAL, "more than 2^31 tiles in one call");
+  if (8 * (4 * (size_t)nmax + 4 * (size_t)h->desc.grid_s + 4) + 16 > 65536)
+    return fail(ISRSGN_EINVAL, "a plan of %d channels with grid_s %d exceeds the 64 KiB workgroup LDS", nmax,
+                h->desc.grid_s);
+  const int total = p->ch_offsets[p->n_batch];
+  uint64_t key = 1469598103934665603ull;
+  key = fnv1a(p->ch_offsets, sizeof(int) * (p->n_batch + 1), key);
+  key = fnv1a(p->f_hz, sizeof(double) * total, key);
+  key = fnv1a(p->rs_hz, sizeof(double) * total, key);
+  for (size_t q = 0; q < h->plans.size(); ++q) {
+    PlanEntry* e = h->plans[q].get();
+    if (e->key == key && e->n_batch == p->n_batch && e->n_total == total &&
+        std::memcmp(e->off.data(), p->ch_offsets, sizeof(int) * (p->n_batch + 1)) == 0 &&
+        std::memcmp(e->f.data(), p->f_hz, sizeof(double) * total) == 0 &&
+        std::memcmp(e->R.data(), p->rs_hz, sizeof(double) * total) == 0) {
+      if (q) std::swap(h->plans[0], h->plans[q]);
+      *out = h->plans[0].get();
+      return ISRSGN_OK;
+    }
+  }
+  auto e = std::make_unique<PlanEntry>();
+  e->key = key;
+  e->off.assign(p->ch_offsets, p->ch_offsets + p->n_batch + 1);
+  e->f.assign(p->f_hz, p->f_hz + total);
+  e->R.assign(p->rs_hz, p->rs_hz + total);
+  e->n_batch = p->n_batch;
+  e->n_total = total;
+  e->n_tiles = ntiles;
+  e->nmax = nmax;
+  std::vector<int64_t> toff(p->n_batch + 1, 0);
+  for (int b = 0; b < p->n_batch; ++b) {
+    const int64_t n = p->ch_offsets[b + 1] - p->ch_offsets[b];
+    toff[b + 1] = toff[b] + n * n;
+  }
+  const int M = h->desc.n_steps;
+  const size_t nt = (size_t)total, nb = (size_t)p->n_batch;
+  bool ok = e->d_off.ensure(sizeof(int) * (nb + 1)) && e->d_toff.ensure(sizeof(int64_t) * (nb + 1)) &&
+            e->d_f.ensure(8 * nt) && e->d_R.ensure(8 * nt) && e->d_alpha.ensure(8 * nt) && e->d_aeff.ensure(8 * nt) &&
+            e->d_gamma.ensure(8 * nt) && e->d_cr.ensure(8 * nt) && e->abar.ensure(8 * nb) &&
+            e->zm.ensure(8 * nb * M) && e->dz.ensure(8 * nb * M) && e->hdz32.ensure(4 * nb * M) &&
+            e->ell64.ensure(8 * nt * M) && e->ellL.ensure(8 * nt) && e->tiles.ensure(8 * (size_t)ntiles) &&
+            e->pnli.ensure(8 * nt) && e->snr.ensure(8 * nt) && e->counter.ensure(64) &&
+            (h->desc.precision != ISRSGN_FP32 || e->lt32.ensure(8 * nt * M));
+  if (!ok) return fail(ISRSGN_ENOMEM, "device allocation failed for a plan of %d channels", total);
+  hipError_t err;
+  if ((err = hipMemcpy(e->d_off.p, p->ch_offsets, sizeof(int) * (nb + 1), hipMemcpyHostToDevice)) != hipSuccess ||
+      (err = hipMemcpy(e->d_toff.p, toff.data(), sizeof(int64_t) * (nb + 1), hipMemcpyHostToDevice)) != hipSuccess ||
+      (err = hipMemcpy(e->d_f.p, p->f_hz, 8 * nt, hipMemcpyHostToDevice)) != hipSuccess ||
+      (err = hipMemcpy(e->d_R.p, p->rs_hz, 8 * nt, hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(err, "plan upload");
+  if ((err = launch_channel_setup(e->view(), h->fp, s)) != hipSuccess) return hip_fail(err, "channel setup");
+  if (h->plans.size() >= 4) h->plans.pop_back();
+  h->plans.insert(h->plans.begin(), std::move(e));
+  *out = h->plans[0].get();
+  return ISRSGN_OK;
+}
+
+void record(isrsgn_fibre* h, int slot, hipStream_t s) {
+  if (!h->timing || !h->ev_ready) return;
+  (void)hipEventRecord(h->ev[slot], s);
+  h->ev_used[slot] = true;
+}
+
+int tile_grid(isrsgn_fibre* h, const PlanEntry* e, bool adjoint) {
+  const int per_cu = tile_blocks_per_cu(h->fp, e->nmax, adjoint);
+  int64_t g = (int64_t)per_cu * h->n_cu;
+  if (g > e->n_tiles) g = e->n_tiles;
+  return (int)(g < 1 ? 1 : g);
+}
+
+// Steps, profile, pair integrals and reduction.  Outputs may be NULL.
+int forward(isrsgn_fibre* h, PlanEntry* e, const double* P, const double* nf, double snr_trx, double* eta,
+            double* pnli, double* tiles_out, double* snr, double* thr, bool keep_states, hipStream_t s) {
+  for (int q = 0; q < 7; ++q) h->ev_used[q] = false;
+  record(h, 0, s);
+  Work w = e->work();
+  if (tiles_out) w.tiles = tiles_out;
+  PlanView pv = e->view();
+  hipError_t err;
+  if ((err = launch_steps(pv, h->fp, P, w, s)) != hipSuccess) return hip_fail(err, "steps");
+  if ((err = launch_profile(pv, h->fp, P, w, keep_states, s)) != hipSuccess) return hip_fail(err, "profile");
+  record(h, 1, s);
+  if ((err = launch_tiles(pv, h->fp, P, w, e->nmax, tile_grid(h, e, false), s)) != hipSuccess)
+    return hip_fail(err, "pair integrals");
+  record(h, 2, s);
+  if ((err = launch_reduce(pv, h->fp, P, nf, snr_trx, w, eta, pnli, snr, thr, s)) != hipSuccess)
+    return hip_fail(err, "reduction");
+  record(h, 3, s);
+  return ISRSGN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int isrsgn_setup_fibre(const isrsgn_fibre_desc* d, isrsgn_fibre** out) {
+  g_err.clear();
+  if (!out) return fail(ISRSGN_EINVAL, "out is NULL");
+  int rc = validate_desc(d);
+  if (rc) return rc;
+  auto h = std::make_unique<isrsgn_fibre>();
+  h->desc = *d;
+  h->tab_f.assign(d->tab_f_hz, d->tab_f_hz + d->n_tab);
+  h->tab_alpha.assign(d->alpha_per_m, d->alpha_per_m + d->n_tab);
+  h->tab_aeff.assign(d->aeff_m2, d->aeff_m2 + d->n_tab);
+  h->desc.tab_f_hz = h->desc.alpha_per_m = h->desc.aeff_m2 = nullptr;
+  FibreParams& fp = h->fp;
+  fp.span = d->span_m;
+  fp.f_ref = d->f_ref_hz;
+  if (d->disp_from_d) {  // eqs. (d), (d_slope), (d_curve) at lambda = c / f_ref
+    const double lam = kC / d->f_ref_hz, w = 2.0 * kPi * kC, D = d->d_s_per_m2, S = d->s_s_per_m3,
+                 Sd = d->sdot_s_per_m4;
+    fp.b2 = -D * lam * lam / w;
+    fp.b3 = lam * lam * lam / (w * w) * (2.0 * D + S * lam);
+    fp.b4 = -(lam * lam * lam * lam) / (w * w * w) * (6.0 * D + 6.0 * S * lam + Sd * lam * lam);
+  } else {
+    fp.b2 = d->beta2;
+    fp.b3 = d->beta3;
+    fp.b4 = d->beta4;
+  }
+  fp.n2 = d->n2_m2_per_w;
+  fp.gamma_const = d->gamma_const_per_w_m;
+  fp.cr = d->cr_per_w_m_hz;
+  fp.aeff_ref = d->aeff_ref_m2;
+  fp.cutoff = d->raman_cutoff_hz;
+  fp.profile = d->profile;
+  fp.photon_ratio = d->photon_ratio ? 1 : 0;
+  fp.n_steps = d->n_steps;
+  fp.grid_s = d->grid_s;
+  fp.grid_v = d->grid_v;
+  fp.ode_sub = d->ode_sub;
+  fp.precision = d->precision;
+  fp.s_decades = d->s_decades;
+  fp.n_tab = d->n_tab;
+  hipError_t err;
+  if ((err = hipGetDevice(&h->device)) != hipSuccess) return hip_fail(err, "hipGetDevice");
+  if ((err = hipDeviceGetAttribute(&h->n_cu, hipDeviceAttributeMultiprocessorCount, h->device)) != hipSuccess)
+    return hip_fail(err, "device attributes");
+  const size_t tb = 8 * (size_t)d->n_tab;
+  if (!h->d_tab_f.ensure(tb) || !h->d_tab_alpha.ensure(tb) || !h->d_tab_aeff.ensure(tb))
+    return fail(ISRSGN_ENOMEM, "device allocation failed for the fibre tables");
+  if ((err = hipMemcpy(h->d_tab_f.p, h->tab_f.data(), tb, hipMemcpyHostToDevice)) != hipSuccess ||
+      (err = hipMemcpy(h->d_tab_alpha.p, h->tab_alpha.data(), tb, hipMemcpyHostToDevice)) != hipSuccess ||
+      (err = hipMemcpy(h->d_tab_aeff.p, h->tab_aeff.data(), tb, hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(err, "table upload");
+  fp.tab_f = h->d_tab_f.as<double>();
+  fp.tab_alpha = h->d_tab_alpha.as<double>();
+  fp.tab_aeff = h->d_tab_aeff.as<double>();
+  *out = h.release();
+  return ISRSGN_OK;
+}
+
+int isrsgn_eta(isrsgn_fibre* h, const isrsgn_plan* plan, const double* P, double* eta, double* pnli, double* tiles,
+               void* stream) {
+  g_err.clear();
+  if (!h || !P || !eta) return fail(ISRSGN_EINVAL, "handle, P_w_dev and eta_dev are required");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  PlanEntry* e;
+  int rc = get_plan(h, plan, s, &e);
+  if (rc) return rc;
+  return forward(h, e, P, nullptr, 0.0, eta, pnli, tiles, nullptr, nullptr, false, s);
+}
+
+int isrsgn_snr(isrsgn_fibre* h, const isrsgn_plan* plan, const double* P, const double* nf, double snr_trx,
+               double* snr, double* thr, void* stream) {
+  g_err.clear();
+  if (!h || !P || !nf || !snr || !thr) return fail(ISRSGN_EINVAL, "handle, P, NF, snr and thr pointers are required");
+  if (!(snr_trx >= 0) || !is_fin(snr_trx)) return fail(ISRSGN_EINVAL, "snr_trx_lin must be finite and >= 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  PlanEntry* e;
+  int rc = get_plan(h, plan, s, &e);
+  if (rc) return rc;
+  return forward(h, e, P, nf, snr_trx, nullptr, nullptr, nullptr, snr, thr, false, s);
+}
+
+int isrsgn_snr_grad(isrsgn_fibre* h, const isrsgn_plan* plan, const double* P, const double* nf, double snr_trx,
+                    double* snr, double* thr, double* dthr, void* stream) {
+  g_err.clear();
+  if (!h || !P || !nf || !snr || !thr || !dthr)
+    return fail(ISRSGN_EINVAL, "handle, P, NF, snr, thr and dthr pointers are required");
+  (void)plan; (void)snr_trx; (void)stream;
+  return fail(ISRSGN_EUNSUPPORTED, "the adjoint is not built yet");
+}
+
+int isrsgn_profile(isrsgn_fibre* h, const isrsgn_plan* plan, const double* P, double* zm, double* dz, double* ell,
+                   double* ellL, void* stream) {
+  g_err.clear();
+  if (!h || !P) return fail(ISRSGN_EINVAL, "handle and P_w_dev are required");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  PlanEntry* e;
+  int rc = get_plan(h, plan, s, &e);
+  if (rc) return rc;
+  Work w = e->work();
+  PlanView pv = e->view();
+  hipError_t err;
+  if ((err = launch_steps(pv, h->fp, P, w, s)) != hipSuccess) return hip_fail(err, "steps");
+  if ((err = launch_profile(pv, h->fp, P, w, false, s)) != hipSuccess) return hip_fail(err, "profile");
+  if ((err = launch_copy_profile(pv, h->fp, w, zm, dz, ell, ellL, s)) != hipSuccess) return hip_fail(err, "copy");
+  return ISRSGN_OK;
+}
+
+int isrsgn_set_timing(isrsgn_fibre* h, int enabled) {
+  g_err.clear();
+  if (!h) return fail(ISRSGN_EINVAL, "handle is NULL");
+  if (enabled && !h->ev_ready) {
+    for (int q = 0; q < 7; ++q) {
+      hipError_t err = hipEventCreate(&h->ev[q]);
+      if (err != hipSuccess) return hip_fail(err, "hipEventCreate");
+    }
+    h->ev_ready = true;
+  }
+  h->timing = enabled != 0;
+  return ISRSGN_OK;
+}
+
+int isrsgn_stage_times(isrsgn_fibre* h, double* ms, int n) {
+  g_err.clear();
+  if (!h || !ms || n < 1) return fail(ISRSGN_EINVAL, "handle and output are required");
+  for (int q = 0; q < n && q < 6; ++q) ms[q] = 0.0;
+  if (!h->ev_ready) return ISRSGN_OK;
+  int last = -1;
+  for (int q = 0; q < 7; ++q) if (h->ev_used[q]) last = q;
+  if (last < 0) return ISRSGN_OK;
+  hipError_t err = hipEventSynchronize(h->ev[last]);
+  if (err != hipSuccess) return hip_fail(err, "hipEventSynchronize");
+  auto span = [&](int a, int b) -> double {
+    if (!h->ev_used[a] || !h->ev_used[b]) return 0.0;
+    float t = 0.f;
+    return hipEventElapsedTime(&t, h->ev[a], h->ev[b]) == hipSuccess ? (double)t : 0.0;
+  };
+  // events: 0 start, 1 after profile, 2 after tiles, 3 after reduce, 4 after adjoint tiles, 5 end of gradient
+  const double st[6] = {span(0, 1), span(1, 2), span(2, 3), span(3, 4), span(4, 5), span(0, last)};
+  for (int q = 0; q < n && q < 6; ++q) ms[q] = st[q];
+  return ISRSGN_OK;
+}
+
+int isrsgn_work_counts(isrsgn_fibre* h, double* out, int n) {
+  g_err.clear();
+  if (!h || !out || n < 1) return fail(ISRSGN_EINVAL, "handle and output are required");
+  for (int q = 0; q < n && q < 3; ++q) out[q] = 0.0;
+  if (h->plans.empty()) return ISRSGN_OK;
+  const PlanEntry* e = h->plans[0].get();
+  unsigned long long nodes = 0;
+  hipError_t err = hipMemcpy(&nodes, e->counter.as<char>() + 32, sizeof(nodes), hipMemcpyDeviceToHost);
+  if (err != hipSuccess) return hip_fail(err, "work counters");
+  const double v[3] = {(double)nodes, (double)nodes * h->desc.n_steps, (double)e->n_tiles};
+  for (int q = 0; q < n && q < 3; ++q) out[q] = v[q];
+  return ISRSGN_OK;
+}
+
+void isrsgn_destroy(isrsgn_fibre* h) {
+  if (!h) return;
+  (void)hipDeviceSynchronize();
+  if (h->ev_ready)
+    for (int q = 0; q < 7; ++q) (void)hipEventDestroy(h->ev[q]);
+  delete h;
+}
+
+const char* isrsgn_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

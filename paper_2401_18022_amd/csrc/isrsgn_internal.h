@@ -1,0 +1,81 @@
+// Internal interface between the host runtime (isrsgn_api.cpp) and the HIP kernels
+// (isrsgn_kernels.hip) of libisrsgn.so.  Not installed; not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace isrsgn {
+
+constexpr int kMaxChannels = 1024;  // per plan (one ODE workgroup of 1024 threads per plan)
+constexpr int kMaxGridS = 1024;     // rows per part held in LDS by the tile kernels
+constexpr int kTileBlock = 256;     // threads per tile workgroup (4 wave64)
+
+// Device view of one (possibly batched) channel plan.
+struct PlanView {
+  int n_batch;
+  int n_total;           // channels over all plans
+  int64_t n_tiles;       // sum over plans of N_b^2
+  const int* off;        // [n_batch + 1] channel offsets
+  const int64_t* toff;   // [n_batch + 1] tile offsets
+  const double* f;       // [n_total] centres
+  const double* R;       // [n_total] symbol rates (rectangular PSD widths)
+  double* alpha;         // [n_total] loss at the centre
+  double* aeff;          // [n_total] effective area at the centre
+  double* gamma;         // [n_total] nonlinear coefficient
+  double* cr;            // [n_total] Raman slope scaled by A_ref / A_eff
+};
+
+struct FibreParams {
+  double span, f_ref, b2, b3, b4;
+  double n2, gamma_const, cr, aeff_ref, cutoff;
+  int profile, photon_ratio, n_steps, grid_s, grid_v, ode_sub, precision;
+  double s_decades;
+  int n_tab;
+  const double* tab_f;      // device copies of the tables
+  const double* tab_alpha;
+  const double* tab_aeff;
+};
+
+// Per-call device workspace (sized for the plan by the host runtime).
+struct Work {
+  double* abar;     // [n_batch] mean loss of the occupied channels
+  double* zm;       // [n_batch * M] step midpoints
+  double* dz;       // [n_batch * M] step widths
+  float* hdz32;     // [n_batch * M] half widths in FP32
+  double* ell64;    // [M * n_total] ln rho(z_m, f_c): plan b block at M * off[b], row-major [m][c]
+  float2* lt32;     // same layout: (ell * log2(e)/2, next - this) for the FP32 integrand
+  double* ellL;     // [n_total] ln rho(L, f_c)
+  double* tiles;    // [n_tiles]
+  double* pnli;     // [n_total]
+  double* snr;      // [n_total]
+  unsigned int* counter;  // work counter of the persistent tile kernels
+  unsigned long long* nodes;  // nodes evaluated by the last forward tile launch
+  // adjoint
+  double* states;   // ODE states, plan b at sstate_off[b]: [(M*2*ode_sub + 1) * N_b]
+  const int64_t* state_off;
+  double* lam;      // [n_total] dT/dP_NLI,i * 16/27 gamma_i^2 R_i  (weight of tile row i)
+  double* gG;       // [n_total] dT/dG_c accumulated by the adjoint tile kernel
+  double* gL;       // [M * n_total] dT/d ell(m, c), same layout as ell64
+  double* gLL;      // [n_total] dT/d ell(L, c)
+  double* gP;       // [n_total] gradient assembly scratch
+};
+
+// Launchers (isrsgn_kernels.hip).  All enqueue on `s` and return the launch status.
+hipError_t launch_channel_setup(const PlanView& pv, const FibreParams& fp, hipStream_t s);
+hipError_t launch_steps(const PlanView& pv, const FibreParams& fp, const double* P, const Work& w, hipStream_t s);
+hipError_t launch_profile(const PlanView& pv, const FibreParams& fp, const double* P, const Work& w,
+                          bool keep_states, hipStream_t s);
+hipError_t launch_tiles(const PlanView& pv, const FibreParams& fp, const double* P, const Work& w,
+                        int nmax, int grid, hipStream_t s);
+hipError_t launch_reduce(const PlanView& pv, const FibreParams& fp, const double* P, const double* nf,
+                         double snr_trx, const Work& w, double* eta, double* pnli_out, double* snr_out,
+                         double* thr_out, hipStream_t s);
+hipError_t launch_copy_profile(const PlanView& pv, const FibreParams& fp, const Work& w, double* zm,
+                               double* dz, double* ell, double* ellL, hipStream_t s);
+hipError_t launch_grad(const PlanView& pv, const FibreParams& fp, const double* P, const double* nf,
+                       double snr_trx, const Work& w, int grid, double* dthr, hipStream_t s,
+                       hipEvent_t mid_event);
+int tile_blocks_per_cu(const FibreParams& fp, int nmax, bool adjoint);
+
+}  // namespace isrsgn
