@@ -17,13 +17,15 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libisrsgn.so")
-SOURCES = ["isrsgn_kernels.hip", "isrsgn_api.cpp"]
+SOURCES = ["isrsgn_kernels.hip", "isrsgn_adjoint.hip", "isrsgn_api.cpp"]
 ARCH = os.environ.get("ISRSGN_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     # no packed FP32 math from the compiler (v_pk_*_f32)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # hardware FP atomics on device (coarse-grained) memory: global/ds add_f32/f64
+    "-munsafe-fp-atomics",
     "-Wno-unused-command-line-argument",
 ]
 

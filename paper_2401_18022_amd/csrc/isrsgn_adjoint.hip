@@ -1,0 +1,494 @@
+// Adjoint of the ISRS GN throughput (arXiv:2401.18022, eq. loss and C = 2 B_ch (-L)) with
+// respect to every launch power: the chain through the SNR reduction, the pair integrals
+// (PSD products and the power term of eq. pk inside eq. psi_fin) and the power profile
+// (closed form or RK4 ODE, differentiated exactly as discretised).
+#include "isrsgn_device.h"
+
+namespace isrsgn {
+namespace {
+
+// ---------------------------------------------------------------------------- upstream weights
+// Per channel i with P_i > 0: N_i = P_NLI,i + P_ASE,i, S0 = P_i / N_i, SNR = S0 (or combined
+// with the transceiver SNR), T_i = 2 R_i log2(1 + SNR).  lam_i = dT/dtile(i,.) =
+// dT/dN_i * 16/27 gamma_i^2 R_i; gP_i starts as the direct dT/dP_i; gLL_i = dT/d ln rho(L, f_i)
+// through the ASE term.
+__global__ void k_grad_prep(PlanView pv, const double* __restrict__ P, const double* __restrict__ nf, double snr_trx,
+                            Work w) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= pv.n_total) return;
+  const double p = P[g], R = pv.R[g], f = pv.f[g], gm = pv.gamma[g];
+  double lamN = 0.0, direct = 0.0, pase = 0.0;
+  if (p > 0.0) {
+    pase = nf[g] * kH * f * R * exp(-w.ellL[g]);
+    const double N = w.pnli[g] + pase, s0 = p / N;
+    double snr = s0, dsnr = 1.0;
+    if (snr_trx > 0.0) {
+      snr = 1.0 / (1.0 / s0 + 1.0 / snr_trx);
+      dsnr = (snr / s0) * (snr / s0);
+    }
+    const double u = 2.0 * R / ((1.0 + snr) * 0.69314718055994530942) * dsnr;  // dT/dS0
+    lamN = -u * s0 / N;
+    direct = u / N;
+  }
+  w.lam[g] = lamN * (16.0 / 27.0) * gm * gm * R;
+  w.gP[g] = direct;
+  w.gLL[g] = -lamN * pase;
+  w.gG[g] = 0.0;
+}
+
+__global__ void k_fill(double* x, int64_t n) {
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+    x[q] = 0.0;
+}
+
+__global__ void k_zero_counter2(unsigned int* c) { *c = 0u; }
+
+// ---------------------------------------------------------------------------- adjoint pair integrals
+// For every node of tile (i,k) with upstream weight lam_i:
+//   d/dG_c:   lam w |S|^2 times the other two PSDs, for c in {c1, c2, k}       (LDS histogram)
+//   d/dE_m:   Q_m = lam w G1 G2 Gk Re(conj(S) term_m)  where term_m is the m-th summand of S
+// and dT/d ln rho(m, c) = Q_m times the interpolation weights of f1, f2, f3 (+) and f_i (-),
+// each with the factor 1/2 of eq. (pk) absorbed (linear profile: E_m = ln rho(f3), weight 2).
+//
+// Scatter: after a node batch has S (pass 1), the batch recomputes its terms in chunks of MC
+// steps (pass 2) and stages Q in LDS; then the lanes are re-mapped to (step, node group):
+// each lane walks its group's nodes in row order, keeping running sums while the f1 (f2)
+// segment stays the same and flushing them with one FP64 atomic per (segment, step) when it
+// changes -- along a row f1 and f2 move monotonically, so runs are long.  The f3 and f_i
+// contributions only touch channels k-1, k, k+1 and i: they accumulate in LDS per tile.
+struct AdjMeta {
+  int s1, s2, valid, pad;
+  float t1, t2, w3a, w3b;
+  float w3c, wi, pad2, pad3;
+};
+
+template <int kPrec>
+struct AdjCfg {
+  using real = float;
+  static constexpr int MC = 16;
+};
+template <>
+struct AdjCfg<1> {
+  using real = double;
+  static constexpr int MC = 8;
+};
+
+__host__ __device__ inline size_t adjoint_lds_bytes(int nmax, int gs, int M, int prec) {
+  const int mc = prec == 0 ? 16 : 8;
+  const size_t rb = prec == 0 ? 4 : 8;
+  return sizeof(double) * (4 * (size_t)nmax + 4 * (size_t)gs + (size_t)nmax + 4 * (size_t)M + 8) +
+         4 * (size_t)mc * 65 * rb + 4 * 64 * sizeof(AdjMeta) + 16;
+}
+
+struct AdjArgs {
+  PlanView pv;
+  FibreParams fp;
+  const double* P;
+  Work w;
+  int nmax;
+};
+
+template <int kPrec, bool kLinear>
+__global__ void __launch_bounds__(kTileBlock) k_adjoint(AdjArgs A) {
+  using real = typename AdjCfg<kPrec>::real;
+  constexpr int MC = AdjCfg<kPrec>::MC;
+  constexpr int NG = 64 / MC;  // node groups per wave in the re-mapped phase
+  extern __shared__ __align__(16) char smem_raw[];
+  const int nmax = A.nmax, GS = A.fp.grid_s, GV = A.fp.grid_v, M = A.fp.n_steps, tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  double* d = reinterpret_cast<double*>(smem_raw);
+  const ChanLds ch{d, d + nmax, d + 2 * nmax, d + 3 * nmax};
+  d += 4 * nmax;
+  const RowLds rw{d, d + GS, d + 2 * GS, d + 3 * GS};
+  d += 4 * GS;
+  double* gGl = d;
+  d += nmax;
+  double* tacc = d;  // [4][M]: channels k-1, k, k+1, i
+  d += 4 * M;
+  double* red = d;
+  d += 8;
+  real* stage = reinterpret_cast<real*>(d);  // [4 waves][MC][65] (odd row stride: no bank conflicts)
+  AdjMeta* meta = reinterpret_cast<AdjMeta*>(stage + 4 * MC * 65);  // [4 waves][64]
+  unsigned int* tile_slot = reinterpret_cast<unsigned int*>(meta + 4 * 64);
+  const PlanView& pv = A.pv;
+  unsigned int* counter = A.w.counter + 2;
+  int cur_b = -1;
+  for (;;) {
+    if (tid == 0) *tile_slot = atomicAdd(counter, 1u);
+    __syncthreads();
+    const unsigned int t = *tile_slot;
+    if ((int64_t)t >= pv.n_tiles) break;
+    int b, i, k;
+    decode_tile(pv, t, &b, &i, &k);
+    const int o = pv.off[b], n = pv.off[b + 1] - o;
+    const double lam = A.w.lam[o + i];
+    if (lam == 0.0) {  // COI outside the throughput (an empty channel): nothing flows back
+      __syncthreads();
+      continue;
+    }
+    if (b != cur_b) {
+      load_channels(ch, pv, A.P, o, n);
+      cur_b = b;
+    }
+    for (int c = tid; c < n; c += kTileBlock) gGl[c] = 0.0;
+    for (int q = tid; q < 4 * M; q += kTileBlock) tacc[q] = 0.0;
+    __syncthreads();
+    const TileGeo g = tile_geo(ch, n, i, k, A.fp.f_ref);
+    const double* zm = A.w.zm + (size_t)b * M;
+    const double* dz = A.w.dz + (size_t)b * M;
+    const float* hdz = A.w.hdz32 + (size_t)b * M;
+    double* gL = A.w.gL + (size_t)M * o;  // [c][m]
+    double gk_acc = 0.0;
+    for (int part = kQ1; part <= kQ4; ++part) {
+      if (!layout_rows(rw, g, part, GS, GV, A.fp.s_decades)) continue;
+      __syncthreads();
+      const int64_t nodes = (int64_t)GS * GV;
+      for (int64_t base = 0; base < nodes; base += kTileBlock) {
+        const int64_t q = base + tid;
+        Node nd;
+        const bool valid = q < nodes && make_node(ch, rw, g, n, k, part, (int)(q / GV), (int)(q % GV), A.fp, &nd);
+        // pass 1: S
+        real sr = 0, si = 0;
+        Term32 t32;
+        Term64 t64;
+        if (valid) {
+          if (kPrec == 0) {
+            t32 = term32_setup(nd, i);
+            const float2* tab = A.w.lt32 + (size_t)M * o;
+            for (int m = 0; m < M; ++m) {
+              const float2 a = term32<kLinear>(t32, m, zm, hdz, tab, n);
+              sr += a.x;
+              si += a.y;
+            }
+          } else {
+            t64 = term64_setup(nd, i);
+            const double* tab = A.w.ell64 + (size_t)M * o;
+            for (int m = 0; m < M; ++m) {
+              const double2 a = term64<kLinear>(t64, m, zm, dz, tab, n);
+              sr += a.x;
+              si += a.y;
+            }
+          }
+          const double s2 = (double)sr * sr + (double)si * si;
+          const double base2 = lam * nd.w * s2;
+          atomicAdd(&gGl[nd.c1], base2 * ch.psd[nd.c2] * g.gk);
+          atomicAdd(&gGl[nd.c2], base2 * ch.psd[nd.c1] * g.gk);
+          gk_acc += base2 * ch.psd[nd.c1] * ch.psd[nd.c2];
+        }
+        const real cq = valid ? (real)(lam * nd.w * nd.gprod) : (real)0;
+        AdjMeta mt{};
+        mt.valid = valid ? 1 : 0;
+        if (valid) {
+          const float t3 = (float)nd.t3;
+          const float wgt = kLinear ? 2.0f : 1.0f;
+          const bool lower = nd.s3 < k;  // segment (k-1, k) or (k, k+1)
+          mt.w3a = lower ? wgt * (1.0f - t3) : 0.0f;
+          mt.w3b = lower ? wgt * t3 : wgt * (1.0f - t3);
+          mt.w3c = lower ? 0.0f : wgt * t3;
+          if (n == 1) { mt.w3a = 0.0f; mt.w3b = wgt; mt.w3c = 0.0f; }
+          mt.s1 = kLinear ? -1 : nd.s1;
+          mt.s2 = kLinear ? -1 : nd.s2;
+          mt.t1 = (float)nd.t1;
+          mt.t2 = (float)nd.t2;
+          mt.wi = kLinear ? 0.0f : 1.0f;
+        }
+        meta[wv * 64 + lane] = mt;
+        // pass 2 in chunks of MC steps
+        for (int m0 = 0; m0 < M; m0 += MC) {
+#pragma unroll
+          for (int mm = 0; mm < MC; ++mm) {
+            const int m = m0 + mm;
+            real qv = 0;
+            if (valid && m < M) {
+              if (kPrec == 0) {
+                const float2 a = term32<kLinear>(t32, m, zm, hdz, A.w.lt32 + (size_t)M * o, n);
+                qv = (real)(cq * (sr * a.x + si * a.y));
+              } else {
+                const double2 a = term64<kLinear>(t64, m, zm, dz, A.w.ell64 + (size_t)M * o, n);
+                qv = (real)(cq * (sr * a.x + si * a.y));
+              }
+            }
+            stage[(wv * MC + mm) * 65 + lane] = qv;
+          }
+          __syncthreads();
+          // re-mapped phase: lane -> (step m0 + mm, node group gr)
+          {
+            const int mm = lane % MC, gr = lane / MC, m = m0 + mm;
+            const bool live = m < M;
+            int cur1 = -1, cur2 = -1;
+            double a1lo = 0, a1hi = 0, a2lo = 0, a2hi = 0, x3a = 0, x3b = 0, x3c = 0, xi = 0;
+            for (int it = 0; it < MC; ++it) {
+              const int j = gr * MC + it;
+              const AdjMeta mj = meta[wv * 64 + j];
+              if (!mj.valid) continue;
+              const double qv = (double)stage[(wv * MC + mm) * 65 + j];
+              if (mj.s1 != cur1) {
+                if (live && cur1 >= 0) {
+                  atomicAdd(&gL[(size_t)cur1 * M + m], a1lo);
+                  if (n > 1) atomicAdd(&gL[(size_t)(cur1 + 1) * M + m], a1hi);
+                }
+                cur1 = mj.s1;
+                a1lo = a1hi = 0.0;
+              }
+              if (mj.s2 != cur2) {
+                if (live && cur2 >= 0) {
+                  atomicAdd(&gL[(size_t)cur2 * M + m], a2lo);
+                  if (n > 1) atomicAdd(&gL[(size_t)(cur2 + 1) * M + m], a2hi);
+                }
+                cur2 = mj.s2;
+                a2lo = a2hi = 0.0;
+              }
+              a1lo += qv * (1.0 - mj.t1);
+              a1hi += qv * mj.t1;
+              a2lo += qv * (1.0 - mj.t2);
+              a2hi += qv * mj.t2;
+              x3a += qv * mj.w3a;
+              x3b += qv * mj.w3b;
+              x3c += qv * mj.w3c;
+              xi += qv * mj.wi;
+            }
+            if (live) {
+              if (cur1 >= 0) {
+                atomicAdd(&gL[(size_t)cur1 * M + m], a1lo);
+                if (n > 1) atomicAdd(&gL[(size_t)(cur1 + 1) * M + m], a1hi);
+              }
+              if (cur2 >= 0) {
+                atomicAdd(&gL[(size_t)cur2 * M + m], a2lo);
+                if (n > 1) atomicAdd(&gL[(size_t)(cur2 + 1) * M + m], a2hi);
+              }
+              atomicAdd(&tacc[0 * M + m], x3a);
+              atomicAdd(&tacc[1 * M + m], x3b);
+              atomicAdd(&tacc[2 * M + m], x3c);
+              atomicAdd(&tacc[3 * M + m], xi);
+            }
+          }
+          __syncthreads();
+        }
+      }
+      __syncthreads();
+    }
+    // tile end: flush the per-tile accumulators
+    gk_acc = block_sum(gk_acc, red);
+    if (tid == 0) gGl[k] += gk_acc;
+    __syncthreads();
+    for (int c = tid; c < n; c += kTileBlock)
+      if (gGl[c] != 0.0) atomicAdd(&A.w.gG[o + c], gGl[c]);
+    for (int q = tid; q < 4 * M; q += kTileBlock) {
+      const int which = q / M, m = q % M;
+      const int c = which == 0 ? k - 1 : (which == 1 ? k : (which == 2 ? k + 1 : i));
+      const double v = which == 3 ? -tacc[q] : tacc[q];
+      if (v != 0.0 && c >= 0 && c < n) atomicAdd(&gL[(size_t)c * M + m], v);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------- profile adjoint
+// Closed form: ln rho(z_m, f_c) = -alpha z_m - a_m (f_c - f_ref) - ln N_m with
+// a_m = P_tot C_r L_eff(z_m), N_m = sum_j (P_j/P_tot) E_j(a_m), E_j(a) = exp(-a d_j) sinhc(a R_j/2).
+// With A1_m = sum_c dT/dln rho(m,c) and A2_m = sum_c dT/dln rho(m,c) (f_c - f_ref):
+//   dT/dP_j += sum_m [ -A2_m C L_m - A1_m ((E_j(a_m)/N_m - 1)/P_tot + C L_m D_m / N_m) ],
+//   D_m = sum_j (P_j/P_tot) E_j'(a_m).  Row m == M is the span end.
+__device__ inline double Ej(double a, double dj, double Rj) { return exp(-a * dj) * sinhc(0.5 * a * Rj); }
+__device__ inline double Ejd(double a, double dj, double Rj) {
+  return exp(-a * dj) * (-dj * sinhc(0.5 * a * Rj) + 0.5 * Rj * sinhc_d(0.5 * a * Rj));
+}
+
+__global__ void k_cf_adj_rows(PlanView pv, FibreParams fp, const double* __restrict__ P, Work w, double* coef) {
+  __shared__ double red[16];
+  const int m = blockIdx.x, b = blockIdx.y, o = pv.off[b], n = pv.off[b + 1] - o, M = fp.n_steps;
+  const double z = m < M ? w.zm[b * M + m] : fp.span;
+  const double alpha = pv.alpha[o], cr = pv.cr[o];
+  double pt = 0.0, A1 = 0.0, A2 = 0.0;
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    pt += P[o + c];
+    const double gl = m < M ? w.gL[(size_t)M * o + (size_t)c * M + m] : w.gLL[o + c];
+    A1 += gl;
+    A2 += gl * (pv.f[o + c] - fp.f_ref);
+  }
+  pt = block_sum(pt, red);
+  A1 = block_sum(A1, red);
+  A2 = block_sum(A2, red);
+  double a = 0.0, N = 1.0, D = 0.0, CL = 0.0;
+  if (pt > 0.0) {
+    CL = cr * (alpha > 0 ? -expm1(-alpha * z) / alpha : z);
+    a = pt * CL;
+    double sN = 0.0, sD = 0.0;
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+      const double dj = pv.f[o + c] - fp.f_ref, Rj = pv.R[o + c], wj = P[o + c] / pt;
+      sN += wj * Ej(a, dj, Rj);
+      sD += wj * Ejd(a, dj, Rj);
+    }
+    N = block_sum(sN, red);
+    D = block_sum(sD, red);
+  }
+  if (threadIdx.x == 0) {
+    double* cf = coef + ((size_t)b * (M + 1) + m) * 8;
+    cf[0] = a; cf[1] = N; cf[2] = D; cf[3] = A1; cf[4] = A2; cf[5] = CL; cf[6] = pt;
+  }
+}
+
+__global__ void k_cf_adj_channels(PlanView pv, FibreParams fp, Work w, const double* coef) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= pv.n_total) return;
+  const int b = plan_of_channel(pv, g), M = fp.n_steps;
+  const double dj = pv.f[g] - fp.f_ref, Rj = pv.R[g];
+  double acc = 0.0;
+  for (int m = 0; m <= M; ++m) {
+    const double* cf = coef + ((size_t)b * (M + 1) + m) * 8;
+    const double a = cf[0], N = cf[1], D = cf[2], A1 = cf[3], A2 = cf[4], CL = cf[5], pt = cf[6];
+    if (!(pt > 0.0)) continue;
+    acc += -A2 * CL - A1 * ((Ej(a, dj, Rj) / N - 1.0) / pt + CL * D / N);
+  }
+  w.gP[g] += acc;
+}
+
+// RK4 ODE adjoint, one block of 1024 threads per plan.  The forward stored ell at the start of
+// every sub-step; going backwards, each sub-step recomputes its stages and applies the exact
+// transpose of RK4, with the vector-Jacobian product of f_k(ell) = -alpha_k + sum_j g_kj P_j e^ell_j:
+//   (J^T v)_j = P_j e^ell_j s_j,  dT/dP_j += e^ell_j s_j,  s_j = sum_k g_kj v_k,
+// where k ranges over j's loss window (k gains from j) and gain window (k feeds j); s_j comes from
+// prefix sums of C_r,k v_k, C_r,k v_k (f_k - f_mid), C_r,k v_k (f_k - f_mid)^2.
+__device__ inline double ode_rhs_a(const OdeChan& ch, int c, double ell, bool active, int photon, OdeShared& sh) {
+  double p = active ? ch.p0 * exp(ell) : 0.0;
+  double a = p, bb = ch.ft * p, cc = active ? p / ch.f : 0.0;
+  block_scan3(a, bb, cc, sh);
+  __syncthreads();
+  if (active) { sh.sA[c] = a; sh.sB[c] = bb; sh.sC[c] = cc; }
+  __syncthreads();
+  double r = 0.0;
+  if (active) {
+    double gA, gB, gC, lA, lB, lC;
+    window_above(sh, ch, c, &gA, &gB, &gC);
+    window_below(sh, ch, c, &lA, &lB, &lC);
+    const double gain = ch.cr * (gB - ch.ft * gA);
+    const double loss = photon ? ch.cr * ch.f * (ch.f * lC - lA) : ch.cr * (ch.ft * lA - lB);
+    r = -ch.alpha + gain - loss;
+  }
+  __syncthreads();
+  return r;
+}
+
+// Returns e^ell s (so that J^T v = P0 * result and dT/dP0 += result).
+__device__ inline double ode_vjp(const OdeChan& ch, int c, double ell, double v, bool active, int photon,
+                                 double fmid, OdeShared& sh) {
+  const double wv = active ? ch.cr * v : 0.0;
+  double a = wv, bb = wv * ch.ft, cc = wv * ch.ft * ch.ft;
+  block_scan3(a, bb, cc, sh);
+  __syncthreads();
+  if (active) { sh.sA[c] = a; sh.sB[c] = bb; sh.sC[c] = cc; }
+  __syncthreads();
+  double r = 0.0;
+  if (active) {
+    double gA, gB, gC, lA, lB, lC;
+    window_below(sh, ch, c, &lA, &lB, &lC);  // k gains from c
+    window_above(sh, ch, c, &gA, &gB, &gC);  // k feeds c
+    double s = ch.ft * lA - lB;
+    if (photon) s -= (gC + (fmid - ch.ft) * gB - ch.ft * fmid * gA) / ch.f;
+    else s -= gB - ch.ft * gA;
+    r = exp(ell) * s;
+  }
+  __syncthreads();
+  return r;
+}
+
+__global__ void __launch_bounds__(1024) k_ode_adjoint(PlanView pv, FibreParams fp, const double* __restrict__ P,
+                                                      Work w) {
+  __shared__ OdeShared sh;
+  const int b = blockIdx.x, o = pv.off[b], n = pv.off[b + 1] - o, M = fp.n_steps, c = threadIdx.x;
+  const bool active = c < n;
+  const double fmid = 0.5 * (pv.f[o] + pv.f[o + n - 1]);
+  OdeChan ch{};
+  if (active) ch = ode_chan(pv, fp, P, o, n, c, fmid);
+  const int sub = fp.ode_sub, ph = fp.photon_ratio;
+  const double* st = w.states + w.state_off[b];
+  double yb = active ? w.gLL[o + c] : 0.0, pb = 0.0;
+  int step = M * 2 * sub;
+  for (int m = M - 1; m >= 0; --m) {
+    const double h = w.dz[b * M + m] / (2.0 * sub);
+    for (int half = 1; half >= 0; --half) {
+      if (half == 0 && active) yb += w.gL[(size_t)M * o + (size_t)c * M + m];  // ell recorded at z_m
+      for (int q = 0; q < sub; ++q) {
+        --step;
+        const double y = active ? st[(size_t)step * n + c] : 0.0;
+        const double k1 = ode_rhs_a(ch, c, y, active, ph, sh);
+        const double u2 = y + 0.5 * h * k1;
+        const double k2 = ode_rhs_a(ch, c, u2, active, ph, sh);
+        const double u3 = y + 0.5 * h * k2;
+        const double k3 = ode_rhs_a(ch, c, u3, active, ph, sh);
+        const double u4 = y + h * k3;
+        double kb4 = yb * (h / 6.0), kb3 = yb * (h / 3.0), kb2 = yb * (h / 3.0), kb1 = yb * (h / 6.0);
+        double ybn = yb;
+        double e = ode_vjp(ch, c, u4, kb4, active, ph, fmid, sh);
+        ybn += ch.p0 * e; kb3 += h * ch.p0 * e; pb += e;
+        e = ode_vjp(ch, c, u3, kb3, active, ph, fmid, sh);
+        ybn += ch.p0 * e; kb2 += 0.5 * h * ch.p0 * e; pb += e;
+        e = ode_vjp(ch, c, u2, kb2, active, ph, fmid, sh);
+        ybn += ch.p0 * e; kb1 += 0.5 * h * ch.p0 * e; pb += e;
+        e = ode_vjp(ch, c, y, kb1, active, ph, fmid, sh);
+        ybn += ch.p0 * e; pb += e;
+        yb = ybn;
+      }
+    }
+  }
+  if (active) w.gP[o + c] += pb;
+}
+
+__global__ void k_grad_final(PlanView pv, Work w, double* dthr) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= pv.n_total) return;
+  dthr[g] = w.gP[g] + w.gG[g] / pv.R[g];
+}
+
+}  // namespace
+
+size_t adjoint_lds(int nmax, int gs, int M, int prec) { return adjoint_lds_bytes(nmax, gs, M, prec); }
+
+int adjoint_blocks_per_cu(const FibreParams& fp, int nmax) {
+  int nb = 0;
+  const size_t shm = adjoint_lds_bytes(nmax, fp.grid_s, fp.n_steps, fp.precision);
+  hipError_t e;
+  if (fp.precision == 0)
+    e = fp.profile == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adjoint<0, true>, kTileBlock, shm)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adjoint<0, false>, kTileBlock, shm);
+  else
+    e = fp.profile == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adjoint<1, true>, kTileBlock, shm)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adjoint<1, false>, kTileBlock, shm);
+  if (e != hipSuccess || nb < 1) nb = 1;
+  return nb;
+}
+
+hipError_t launch_grad(const PlanView& pv, const FibreParams& fp, const double* P, const double* nf, double snr_trx,
+                       const Work& w, int nmax, int grid, double* coef, double* dthr, hipStream_t s,
+                       hipEvent_t mid_event) {
+  const int M = fp.n_steps;
+  hipLaunchKernelGGL(k_grad_prep, dim3((pv.n_total + 255) / 256), dim3(256), 0, s, pv, P, nf, snr_trx, w);
+  const int64_t ngl = (int64_t)M * pv.n_total;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)((ngl + 255) / 256 < 4096 ? (ngl + 255) / 256 : 4096)), dim3(256), 0, s,
+                     w.gL, ngl);
+  hipLaunchKernelGGL(k_zero_counter2, dim3(1), dim3(1), 0, s, w.counter + 2);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  AdjArgs a{pv, fp, P, w, nmax};
+  const size_t shm = adjoint_lds_bytes(nmax, fp.grid_s, M, fp.precision);
+  if (fp.precision == 0) {
+    if (fp.profile == 0) hipLaunchKernelGGL((k_adjoint<0, true>), dim3(grid), dim3(kTileBlock), shm, s, a);
+    else hipLaunchKernelGGL((k_adjoint<0, false>), dim3(grid), dim3(kTileBlock), shm, s, a);
+  } else {
+    if (fp.profile == 0) hipLaunchKernelGGL((k_adjoint<1, true>), dim3(grid), dim3(kTileBlock), shm, s, a);
+    else hipLaunchKernelGGL((k_adjoint<1, false>), dim3(grid), dim3(kTileBlock), shm, s, a);
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (mid_event) (void)hipEventRecord(mid_event, s);
+  if (fp.profile == 0) {
+    hipLaunchKernelGGL(k_cf_adj_rows, dim3(M + 1, pv.n_batch), dim3(256), 0, s, pv, fp, P, w, coef);
+    hipLaunchKernelGGL(k_cf_adj_channels, dim3((pv.n_total + 255) / 256), dim3(256), 0, s, pv, fp, w,
+                       (const double*)coef);
+  } else {
+    hipLaunchKernelGGL(k_ode_adjoint, dim3(pv.n_batch), dim3(1024), 0, s, pv, fp, P, w);
+  }
+  hipLaunchKernelGGL(k_grad_final, dim3((pv.n_total + 255) / 256), dim3(256), 0, s, pv, w, dthr);
+  return hipGetLastError();
+}
+
+}  // namespace isrsgn

@@ -77,7 +77,7 @@ struct PlanEntry {
   DevBuf d_off, d_toff, d_f, d_R, d_alpha, d_aeff, d_gamma, d_cr;
   // workspace
   DevBuf abar, zm, dz, hdz32, ell64, lt32, ellL, tiles, pnli, snr, counter;
-  DevBuf states, state_off, lam, gG, gL, gLL, gP;
+  DevBuf states, state_off, lam, gG, gL, gLL, gP, coef;
   bool grad_ready = false;
   PlanView view() const {
     PlanView v;
@@ -368,8 +368,43 @@ int isrsgn_snr_grad(isrsgn_fibre* h, const isrsgn_plan* plan, const double* P, c
   g_err.clear();
   if (!h || !P || !nf || !snr || !thr || !dthr)
     return fail(ISRSGN_EINVAL, "handle, P, NF, snr, thr and dthr pointers are required");
-  (void)plan; (void)snr_trx; (void)stream;
-  return fail(ISRSGN_EUNSUPPORTED, "the adjoint is not built yet");
+  if (!(snr_trx >= 0) || !is_fin(snr_trx)) return fail(ISRSGN_EINVAL, "snr_trx_lin must be finite and >= 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  PlanEntry* e;
+  int rc = get_plan(h, plan, s, &e);
+  if (rc) return rc;
+  const int M = h->desc.n_steps;
+  if (adjoint_lds(e->nmax, h->desc.grid_s, M, h->desc.precision) > 65536)
+    return fail(ISRSGN_EUNSUPPORTED, "the adjoint of a %d-channel plan with grid_s %d and %d steps exceeds 64 KiB LDS",
+                e->nmax, h->desc.grid_s, M);
+  if (!e->grad_ready) {
+    const size_t nt = (size_t)e->n_total, nb = (size_t)e->n_batch;
+    std::vector<int64_t> soff(nb + 1, 0);
+    const bool ode = h->desc.profile == ISRSGN_PROFILE_ODE;
+    for (size_t b = 0; b < nb; ++b) {
+      const int64_t n = e->off[b + 1] - e->off[b];
+      soff[b + 1] = soff[b] + (ode ? ((int64_t)M * 2 * h->desc.ode_sub + 1) * n : 0);
+    }
+    bool ok = e->lam.ensure(8 * nt) && e->gG.ensure(8 * nt) && e->gL.ensure(8 * nt * M) && e->gLL.ensure(8 * nt) &&
+              e->gP.ensure(8 * nt) && e->coef.ensure(8 * 8 * nb * (M + 1)) && e->state_off.ensure(8 * (nb + 1)) &&
+              e->states.ensure(8 * (size_t)soff[nb]);
+    if (!ok) return fail(ISRSGN_ENOMEM, "device allocation failed for the adjoint workspace");
+    hipError_t err = hipMemcpy(e->state_off.p, soff.data(), 8 * (nb + 1), hipMemcpyHostToDevice);
+    if (err != hipSuccess) return hip_fail(err, "state offsets");
+    e->grad_ready = true;
+  }
+  rc = forward(h, e, P, nf, snr_trx, nullptr, nullptr, nullptr, snr, thr, h->desc.profile == ISRSGN_PROFILE_ODE, s);
+  if (rc) return rc;
+  const int per_cu = adjoint_blocks_per_cu(h->fp, e->nmax);
+  int64_t grid = (int64_t)per_cu * h->n_cu;
+  if (grid > e->n_tiles) grid = e->n_tiles;
+  hipEvent_t mid = (h->timing && h->ev_ready) ? h->ev[4] : nullptr;
+  if (mid) h->ev_used[4] = true;
+  hipError_t err = launch_grad(e->view(), h->fp, P, nf, snr_trx, e->work(), e->nmax, (int)(grid < 1 ? 1 : grid),
+                               e->coef.as<double>(), dthr, s, mid);
+  if (err != hipSuccess) return hip_fail(err, "adjoint");
+  record(h, 5, s);
+  return ISRSGN_OK;
 }
 
 int isrsgn_profile(isrsgn_fibre* h, const isrsgn_plan* plan, const double* P, double* zm, double* dz, double* ell,

@@ -1,0 +1,426 @@
+// Device helpers shared by the forward and adjoint kernels of libisrsgn.so (internal).
+//
+// Model: arXiv:2401.18022 -- step sum eq. (slow_vary) inside eq. (psi_fin), power term
+// eq. (pk), phase mismatch eq. (phi), hyperbolic coordinates eqs. (q1)-(q4).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "isrsgn_internal.h"
+
+namespace isrsgn {
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kC = 299792458.0;
+constexpr double kH = 6.62607015e-34;
+constexpr double kLn10 = 2.302585092994045684;
+constexpr double kHalfLog2e = 0.72134752044448170368;  // log2(e) / 2
+
+// ---------------------------------------------------------------------------- reductions
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum over the block (a multiple of 64 threads); fixed order, result on every thread.
+__device__ inline double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int q = 0; q < nw; ++q) t += red[q];
+  __syncthreads();
+  return t;
+}
+
+__device__ inline double tab_at(int n, const double* xs, const double* ys, double x) {
+  if (n == 1 || x <= xs[0]) return ys[0];
+  if (x >= xs[n - 1]) return ys[n - 1];
+  int lo = 0, hi = n - 1;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (xs[mid] <= x) lo = mid; else hi = mid;
+  }
+  return ys[lo] + (x - xs[lo]) / (xs[hi] - xs[lo]) * (ys[hi] - ys[lo]);
+}
+
+__device__ inline int plan_of_channel(const PlanView& pv, int g) {
+  int lo = 0, hi = pv.n_batch;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (pv.off[mid] <= g) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ inline double sinhc(double x) {
+  if (fabs(x) < 1e-4) { double x2 = x * x; return 1.0 + x2 / 6.0 + x2 * x2 / 120.0; }
+  return sinh(x) / x;
+}
+
+// d sinhc / dx
+__device__ inline double sinhc_d(double x) {
+  if (fabs(x) < 1e-3) { double x2 = x * x; return x / 3.0 + x * x2 / 30.0 + x * x2 * x2 / 840.0; }
+  return (x * cosh(x) - sinh(x)) / (x * x);
+}
+
+// ---------------------------------------------------------------------------- ODE helpers
+// Block of 1024 threads, thread c owning channel c of the plan.
+struct OdeShared {
+  double sA[kMaxChannels], sB[kMaxChannels], sC[kMaxChannels];
+  double wt[3][16];
+};
+
+// Inclusive block-wide prefix sums of three values (fixed order).
+__device__ inline void block_scan3(double& a, double& bb, double& c, OdeShared& sh) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    double ta = __shfl_up(a, o, 64), tb = __shfl_up(bb, o, 64), tc = __shfl_up(c, o, 64);
+    if (lane >= o) { a += ta; bb += tb; c += tc; }
+  }
+  if (lane == 63) { sh.wt[0][wid] = a; sh.wt[1][wid] = bb; sh.wt[2][wid] = c; }
+  __syncthreads();
+  double pa = 0.0, pb = 0.0, pc = 0.0;
+  for (int q = 0; q < wid; ++q) { pa += sh.wt[0][q]; pb += sh.wt[1][q]; pc += sh.wt[2][q]; }
+  a += pa; bb += pb; c += pc;
+}
+
+// Per-channel constants of the Raman ODEs and the index windows of its gain and loss sums:
+// channel c gains from j in (c, ghi] (0 < f_j - f_c <= cut) and feeds j in [llo, c).
+struct OdeChan {
+  double f, ft, alpha, cr, p0;
+  int ghi, llo;
+};
+
+__device__ inline OdeChan ode_chan(const PlanView& pv, const FibreParams& fp, const double* P, int o, int n, int c,
+                                   double fmid) {
+  OdeChan ch{};
+  ch.f = pv.f[o + c];
+  ch.ft = ch.f - fmid;
+  ch.alpha = pv.alpha[o + c];
+  ch.cr = pv.cr[o + c];
+  ch.p0 = P[o + c];
+  const double cut = fp.cutoff;
+  int lo = c, hi = n;  // last j with f_j - f_c <= cut
+  if (cut <= 0) lo = n - 1;
+  else
+    while (hi - lo > 1) { int mid = (lo + hi) >> 1; if (pv.f[o + mid] - ch.f <= cut) lo = mid; else hi = mid; }
+  ch.ghi = lo;
+  int l2 = -1, h2 = c;  // first j with f_c - f_j <= cut
+  if (cut <= 0) h2 = 0;
+  else
+    while (h2 - l2 > 1) { int mid = (l2 + h2) >> 1; if (ch.f - pv.f[o + mid] <= cut) h2 = mid; else l2 = mid; }
+  ch.llo = h2;
+  return ch;
+}
+
+// Window sums of the prefix arrays: (c, ghi] and [llo, c).
+__device__ inline void window_above(const OdeShared& sh, const OdeChan& ch, int c, double* A, double* B, double* Cc) {
+  *A = *B = *Cc = 0.0;
+  if (ch.ghi > c) {
+    *A = sh.sA[ch.ghi] - sh.sA[c];
+    *B = sh.sB[ch.ghi] - sh.sB[c];
+    *Cc = sh.sC[ch.ghi] - sh.sC[c];
+  }
+}
+__device__ inline void window_below(const OdeShared& sh, const OdeChan& ch, int c, double* A, double* B, double* Cc) {
+  *A = *B = *Cc = 0.0;
+  if (c > ch.llo) {
+    const double bA = ch.llo > 0 ? sh.sA[ch.llo - 1] : 0.0;
+    const double bB = ch.llo > 0 ? sh.sB[ch.llo - 1] : 0.0;
+    const double bC = ch.llo > 0 ? sh.sC[ch.llo - 1] : 0.0;
+    *A = sh.sA[c - 1] - bA;
+    *B = sh.sB[c - 1] - bB;
+    *Cc = sh.sC[c - 1] - bC;
+  }
+}
+
+// ---------------------------------------------------------------------------- tile geometry
+// Parts of tile (i,k) in offsets (x, y) = (f1 - f_i, f2 - f_i) with x + y in [slo, shi):
+//   Q1: x = r e^v, y = r e^-v, v >= 0 (fold about x = y)
+//   Q3: x = -r e^v, y = -r e^-v, v >= 0 (fold)
+//   Q4: x = r e^v, y = -r e^-v (stands for the mirror part Q2 as well)
+// r = sqrt(|x y|) = e^(s/2).  sup|x y| fixes the top of the s window.
+enum { kQ1 = 0, kQ3 = 1, kQ4 = 2 };
+
+__device__ inline bool part_umax(int part, double slo, double shi, double xp, double xn, double* umax) {
+  if (part == kQ1) {
+    if (shi <= 0 || xp <= 0) return false;
+    double lo = fmax(slo, 0.0);
+    if (lo >= 2.0 * xp) return false;
+    double m = fmin(0.5 * shi, xp);
+    *umax = m * m;
+    return *umax > 0;
+  }
+  if (part == kQ3) {
+    if (slo >= 0 || xn <= 0) return false;
+    double lo = fmax(-shi, 0.0), hi = -slo;
+    if (lo >= 2.0 * xn) return false;
+    double m = fmin(0.5 * hi, xn);
+    *umax = m * m;
+    return *umax > 0;
+  }
+  if (xp <= 0 || xn <= 0) return false;
+  double best = 0.0;
+  double ulo = fmax(0.0, xp - shi), uhi = fmin(xn, xp - slo);
+  if (uhi > ulo) best = fmax(best, xp * uhi);
+  double xlo = fmax(0.0, xn + slo), xhi = fmin(xp, xn + shi);
+  if (xhi > xlo) best = fmax(best, xhi * xn);
+  if (!(best > 0)) return false;
+  *umax = best;
+  return true;
+}
+
+__device__ inline bool part_vrange(int part, double r, double slo, double shi, double xp, double xn, double* vlo,
+                                   double* vhi) {
+  if (part == kQ1 || part == kQ3) {
+    const double lo = part == kQ1 ? fmax(slo, 0.0) : fmax(-shi, 0.0);
+    const double hi = part == kQ1 ? shi : -slo;
+    const double lim = part == kQ1 ? xp : xn;
+    const double chi = hi / (2.0 * r);
+    if (!(chi > 1.0)) return false;
+    const double clo = lo / (2.0 * r);
+    *vlo = clo > 1.0 ? acosh(clo) : 0.0;
+    *vhi = fmin(acosh(chi), log(lim / r));
+    return *vhi > *vlo;
+  }
+  *vlo = fmax(asinh(slo / (2.0 * r)), log(r / xn));
+  *vhi = fmin(asinh(shi / (2.0 * r)), log(xp / r));
+  return *vhi > *vlo;
+}
+
+// Channel data of the current plan in LDS.
+struct ChanLds {
+  double* lo_edge;  // f_c - R_c/2
+  double* hi_edge;  // f_c + R_c/2
+  double* fc;
+  double* psd;      // G_c = P_c / R_c
+};
+
+// Row layout of the current part in LDS: v_lo, dv (0: empty row), r, node weight.
+struct RowLds {
+  double *vlo, *dv, *r, *w;
+};
+
+__device__ inline void load_channels(const ChanLds& ch, const PlanView& pv, const double* P, int o, int n) {
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    const double f = pv.f[o + c], R = pv.R[o + c];
+    ch.fc[c] = f;
+    ch.lo_edge[c] = f - 0.5 * R;
+    ch.hi_edge[c] = f + 0.5 * R;
+    ch.psd[c] = P[o + c] / R;
+  }
+}
+
+// Channel whose band [f_c - R_c/2, f_c + R_c/2) holds F, or -1.
+__device__ inline int find_channel(const ChanLds& ch, int n, double F) {
+  if (F < ch.lo_edge[0]) return -1;
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (ch.lo_edge[mid] <= F) lo = mid; else hi = mid;
+  }
+  return F < ch.hi_edge[lo] ? lo : -1;
+}
+
+// Interpolation segment and weight of ln rho at F, given the channel c that holds F.
+__device__ inline void segment(const ChanLds& ch, int n, int c, double F, int* seg, double* t) {
+  if (n == 1) { *seg = 0; *t = 0.0; return; }
+  int s = F >= ch.fc[c] ? c : c - 1;
+  s = s < 0 ? 0 : (s > n - 2 ? n - 2 : s);
+  *seg = s;
+  *t = (F - ch.fc[s]) / (ch.fc[s + 1] - ch.fc[s]);
+}
+
+// eq. (phi): phase mismatch per metre for offsets x, y and COI offset w from f_ref.
+__device__ inline double phase_mismatch(double x, double y, double w, double b2, double b3, double b4) {
+  const double p4 = x * x + 1.5 * x * y + y * y + 3.0 * x * w + 3.0 * y * w + 3.0 * w * w;
+  return -4.0 * kPi * kPi * x * y * (b2 + kPi * b3 * (x + y + 2.0 * w) + (2.0 * kPi * kPi / 3.0) * b4 * p4);
+}
+
+// Decode a global tile index into (plan, COI, interferer).
+__device__ inline void decode_tile(const PlanView& pv, unsigned int t, int* b, int* i, int* k) {
+  int lo = 0, hi = pv.n_batch;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (pv.toff[mid] <= (int64_t)t) lo = mid; else hi = mid;
+  }
+  const int n = pv.off[lo + 1] - pv.off[lo];
+  const int64_t loc = (int64_t)t - pv.toff[lo];
+  *b = lo;
+  *i = (int)(loc / n);
+  *k = (int)(loc % n);
+}
+
+// Geometry of tile (i,k) of the current plan.
+struct TileGeo {
+  double fi, xp, xn, slo, shi, wi, gk;
+};
+
+__device__ inline TileGeo tile_geo(const ChanLds& ch, int n, int i, int k, double f_ref) {
+  TileGeo g;
+  g.fi = ch.fc[i];
+  g.xp = ch.hi_edge[n - 1] - g.fi;
+  g.xn = g.fi - ch.lo_edge[0];
+  g.slo = ch.lo_edge[k] - g.fi;
+  g.shi = ch.hi_edge[k] - g.fi;
+  g.wi = g.fi - f_ref;
+  g.gk = ch.psd[k];
+  return g;
+}
+
+// Lays out the rows of one part in LDS (all threads of the block); false if the part is empty.
+__device__ inline bool layout_rows(const RowLds& rw, const TileGeo& g, int part, int gs, int gv, double s_decades) {
+  double umax;
+  if (!part_umax(part, g.slo, g.shi, g.xp, g.xn, &umax)) return false;
+  const double smax = log(umax), smin = smax - s_decades * kLn10, ds = (smax - smin) / gs;
+  for (int a = threadIdx.x; a < gs; a += blockDim.x) {
+    const double s = smin + (a + 0.5) * ds, r = exp(0.5 * s);
+    double vlo, vhi;
+    if (part_vrange(part, r, g.slo, g.shi, g.xp, g.xn, &vlo, &vhi)) {
+      const double dv = (vhi - vlo) / gv;
+      rw.vlo[a] = vlo;
+      rw.dv[a] = dv;
+      rw.r[a] = r;
+      rw.w[a] = 2.0 * exp(s) * ds * dv;
+    } else {
+      rw.dv[a] = 0.0;
+    }
+  }
+  return true;
+}
+
+// One node of a part: offsets, channels, interpolation segments, phase rate (revolutions per m).
+struct Node {
+  double w, gprod, phr;
+  int c1, c2, s1, s2, s3;
+  double t1, t2, t3;
+};
+
+__device__ inline bool make_node(const ChanLds& ch, const RowLds& rw, const TileGeo& g, int n, int k, int part,
+                                 int a, int bcol, const FibreParams& fp, Node* nd) {
+  const double dv = rw.dv[a];
+  if (dv == 0.0) return false;
+  const double v = rw.vlo[a] + (bcol + 0.5) * dv, r = rw.r[a];
+  const double ev = exp(v);
+  double x = r * ev, y = r / ev;
+  if (part == kQ3) { x = -x; y = -y; }
+  else if (part == kQ4) { y = -y; }
+  const int c1 = find_channel(ch, n, g.fi + x);
+  const int c2 = find_channel(ch, n, g.fi + y);
+  if (c1 < 0 || c2 < 0) return false;
+  nd->w = rw.w[a];
+  nd->c1 = c1;
+  nd->c2 = c2;
+  nd->gprod = ch.psd[c1] * ch.psd[c2] * g.gk;
+  nd->phr = phase_mismatch(x, y, g.wi, fp.b2, fp.b3, fp.b4) * (0.5 / kPi);
+  segment(ch, n, c1, g.fi + x, &nd->s1, &nd->t1);
+  segment(ch, n, c2, g.fi + y, &nd->s2, &nd->t2);
+  segment(ch, n, k, g.fi + x + y, &nd->s3, &nd->t3);
+  return true;
+}
+
+// ---------------------------------------------------------------------------- step terms
+// Term m of S = sum_m p_m dz_m exp(j phi z_m) sinc(phi dz_m / 2) (eq. slow_vary), returned as
+// (re, im).  p_m = exp(E_m), E_m = [ln rho(f1) + ln rho(f2) + ln rho(f3) - ln rho(f_i)] / 2 (eq. pk);
+// with a profile linear in f (the closed form) E_m = ln rho(f3) exactly.
+//
+// FP32 form: the phase phi z_m is formed in FP64 and reduced to [-1/2, 1/2] revolutions before
+// the FP32 hardware sine/cosine (which take revolutions); the sinc factor uses its Taylor
+// polynomial while |phi dz_m / 2| < 1/2; E_m comes from an FP32 table of ln rho log2(e)/2.
+struct Term32 {
+  double phr;
+  float phrf, inv_piphr, t1, t2, t3;
+  int s1, s2, s3, ci;
+};
+
+__device__ inline Term32 term32_setup(const Node& nd, int i) {
+  Term32 q;
+  q.phr = nd.phr;
+  q.phrf = (float)nd.phr;
+  q.inv_piphr = 1.0f / ((float)kPi * q.phrf);
+  q.t1 = (float)nd.t1;
+  q.t2 = (float)nd.t2;
+  q.t3 = (float)nd.t3;
+  q.s1 = nd.s1;
+  q.s2 = nd.s2;
+  q.s3 = nd.s3;
+  q.ci = i;
+  return q;
+}
+
+template <bool kLinear>
+__device__ inline float2 term32(const Term32& q, int m, const double* __restrict__ zm, const float* __restrict__ hdz,
+                                const float2* __restrict__ tab, int n) {
+  const double tt = q.phr * zm[m];
+  const float fr = (float)(tt - rint(tt));
+  const float sn = __builtin_amdgcn_sinf(fr);
+  const float cs = __builtin_amdgcn_cosf(fr);
+  const float hh = q.phrf * hdz[m];
+  const float u = 2.0f * (float)kPi * hh;
+  const float u2 = u * u;
+  const float dzm = 2.0f * hdz[m];
+  const float apoly = dzm * (1.0f + u2 * (-1.0f / 6.0f + u2 * (1.0f / 120.0f - u2 * (1.0f / 5040.0f))));
+  const float asn = __builtin_amdgcn_sinf(hh - rintf(hh)) * q.inv_piphr;
+  const float amp0 = fabsf(u) < 0.5f ? apoly : asn;
+  const float2* row = tab + (size_t)m * n;
+  float e2;
+  if (kLinear) {
+    const float2 l3 = row[q.s3];
+    e2 = 2.0f * (l3.x + q.t3 * l3.y);
+  } else {
+    const float2 l1 = row[q.s1], l2 = row[q.s2], l3 = row[q.s3];
+    e2 = (l1.x + q.t1 * l1.y) + (l2.x + q.t2 * l2.y) + (l3.x + q.t3 * l3.y) - row[q.ci].x;
+  }
+  const float amp = __builtin_amdgcn_exp2f(e2) * amp0;
+  return make_float2(amp * cs, amp * sn);
+}
+
+// FP64 form of the same term (ocml sincospi / sinpi / exp on the FP64 table).
+struct Term64 {
+  double phr, t1, t2, t3;
+  int s1, s2, s3, ci;
+};
+
+__device__ inline Term64 term64_setup(const Node& nd, int i) {
+  Term64 q;
+  q.phr = nd.phr;
+  q.t1 = nd.t1;
+  q.t2 = nd.t2;
+  q.t3 = nd.t3;
+  q.s1 = nd.s1;
+  q.s2 = nd.s2;
+  q.s3 = nd.s3;
+  q.ci = i;
+  return q;
+}
+
+template <bool kLinear>
+__device__ inline double2 term64(const Term64& q, int m, const double* __restrict__ zm, const double* __restrict__ dz,
+                                 const double* __restrict__ tab, int n) {
+  const double tt = q.phr * zm[m];
+  double sn, cs;
+  sincospi(2.0 * (tt - rint(tt)), &sn, &cs);
+  const double hh = 0.5 * q.phr * dz[m];
+  const double amp0 = hh == 0.0 ? dz[m] : sinpi(2.0 * (hh - rint(hh))) / (kPi * q.phr);
+  const double* row = tab + (size_t)m * n;
+  const int d = n > 1 ? 1 : 0;
+  double e;
+  if (kLinear) {
+    e = row[q.s3] + q.t3 * (row[q.s3 + d] - row[q.s3]);
+  } else {
+    e = 0.5 * ((row[q.s1] + q.t1 * (row[q.s1 + d] - row[q.s1])) + (row[q.s2] + q.t2 * (row[q.s2 + d] - row[q.s2])) +
+               (row[q.s3] + q.t3 * (row[q.s3 + d] - row[q.s3])) - row[q.ci]);
+  }
+  const double amp = exp(e) * amp0;
+  return make_double2(amp * cs, amp * sn);
+}
+
+}  // namespace
+}  // namespace isrsgn

@@ -74,8 +74,10 @@ hipError_t launch_reduce(const PlanView& pv, const FibreParams& fp, const double
 hipError_t launch_copy_profile(const PlanView& pv, const FibreParams& fp, const Work& w, double* zm,
                                double* dz, double* ell, double* ellL, hipStream_t s);
 hipError_t launch_grad(const PlanView& pv, const FibreParams& fp, const double* P, const double* nf,
-                       double snr_trx, const Work& w, int grid, double* dthr, hipStream_t s,
-                       hipEvent_t mid_event);
+                       double snr_trx, const Work& w, int nmax, int grid, double* coef, double* dthr,
+                       hipStream_t s, hipEvent_t mid_event);
+size_t adjoint_lds(int nmax, int gs, int M, int prec);
+int adjoint_blocks_per_cu(const FibreParams& fp, int nmax);
 int tile_blocks_per_cu(const FibreParams& fp, int nmax, bool adjoint);
 
 }  // namespace isrsgn

@@ -1,0 +1,129 @@
+"""GPU adjoint gradient of the throughput against the oracle's forward-mode dual numbers and
+against central finite differences of the FP64 GPU form.
+
+Tolerances: FP64 form 1e-8 relative to the gradient's scale (rounding, atomics order);
+FP32 form 1e-3 relative (the model target), observed ~1e-6.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2401_18022_amd import binding as B
+from paper_2401_18022_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {W.FP64: 1e-8, W.FP32: 1e-3}
+
+
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+def gpu_grad(wl, prec):
+    t = torch()
+    eng = B.Engine(wl.fibre, prec)
+    P = t.tensor(wl.plan.p_w, dtype=t.float64, device="cuda")
+    nf = t.tensor(wl.plan.nf_lin, dtype=t.float64, device="cuda")
+    snr, thr, g = eng.snr_grad(wl.plan, P, nf, wl.plan.snr_trx_lin)
+    t.cuda.synchronize()
+    return snr.cpu().numpy(), thr.cpu().numpy(), g.cpu().numpy()
+
+
+def check_against_duals(wl, prec, directions):
+    print(f"[grad] {wl.name} prec={prec} dirs={len(directions)}", flush=True)
+    snr, thr, g = gpu_grad(wl, prec)
+    o = O.Oracle(wl.fibre, wl.plan)
+    scale = np.abs(g * wl.plan.p_w).sum()
+    for d in directions:
+        r = o.forward_dual(d)
+        assert thr[0] == pytest.approx(r["thr"], rel=1e-5 if prec == W.FP32 else 1e-11)
+        got = float(np.dot(g, d))
+        assert abs(got - r["dthr"]) <= TOL[prec] * scale, (got, r["dthr"], scale)
+    return g
+
+
+@pytest.mark.parametrize("prec", [W.FP64, W.FP32])
+def test_closed_form_gradient_matches_duals(prec):
+    wl = W.config_tiny(grid_s=24, grid_v=24, n_steps=30)
+    wl = wl.with_plan(wl.plan.with_power(wl.plan.p_w * np.array([20, 50, 10, 80, 30])))
+    check_against_duals(wl, prec, [np.eye(5)[c] * wl.plan.p_w[c] for c in range(5)])
+
+
+@pytest.mark.parametrize("prec", [W.FP64, W.FP32])
+def test_ode_gradient_matches_duals(prec):
+    wl = W.random_small(9, seed=3, grid_s=16, grid_v=24, n_steps=20)
+    wl = wl.with_plan(wl.plan.with_power(wl.plan.p_w * 30))
+    rng = np.random.default_rng(7)
+    dirs = [np.eye(9)[c] * wl.plan.p_w[c] for c in (0, 4, 8)] + [rng.normal(size=9) * wl.plan.p_w]
+    check_against_duals(wl, prec, dirs)
+
+
+def test_gradient_with_guard_channels_and_transceiver():
+    wl = W.random_small(8, seed=12, grid_s=16, grid_v=16, n_steps=16)
+    p = wl.plan.p_w * 20
+    p[[2, 5]] = 0.0
+    plan = wl.plan.with_power(p)
+    plan.snr_trx_lin = 100.0
+    wl = wl.with_plan(plan)
+    dirs = [np.eye(8)[c] * 1e-3 for c in (1, 2, 5, 7)]
+    check_against_duals(wl, W.FP64, dirs)
+
+
+def test_cl_band_gradient_matches_duals_reduced_grid():
+    wl = W.config_cl(grid_s=12, grid_v=12, n_steps=16)
+    rng = np.random.default_rng(11)
+    dirs = [rng.normal(size=95) * wl.plan.p_w for _ in range(2)]
+    check_against_duals(wl, W.FP32, dirs)
+
+
+def test_ou_gradient_central_differences_fp64():
+    """O-to-U system (589 ch) at a reduced grid: the adjoint against central differences of the
+    FP64 GPU form at +-1e-3 dB on 8 of the seeded channels."""
+    t = torch()
+    wl = W.config_ou(grid_s=16, grid_v=16, n_steps=24)
+    eng = B.Engine(wl.fibre, W.FP64)
+    P0 = t.tensor(wl.plan.p_w, dtype=t.float64, device="cuda")
+    nf = t.tensor(wl.plan.nf_lin, dtype=t.float64, device="cuda")
+    _, _, g = eng.snr_grad(wl.plan, P0, nf)
+    g = g.cpu().numpy()
+    h = 10 ** (1e-4) - 1
+    for c in W.fd_channels()[:8]:
+        Pp, Pm = P0.clone(), P0.clone()
+        Pp[c] *= 1 + h
+        Pm[c] *= 1 - h
+        tp = eng.snr(wl.plan, Pp, nf)[1].item()
+        tm = eng.snr(wl.plan, Pm, nf)[1].item()
+        fd = (tp - tm) / (2 * h * wl.plan.p_w[c])
+        assert g[c] == pytest.approx(fd, rel=2e-4, abs=1e-9 * np.abs(g).max()), c
+
+
+def test_batched_gradient():
+    plans = [W.random_small(n, seed=60 + n).plan for n in (5, 1, 7)]
+    fb = W.random_small(5, seed=65, grid_s=12, grid_v=12, n_steps=12).fibre
+    wl = W.Workload("grad-batch", fb, W.concat_plans(plans))
+    snr, thr, g = gpu_grad(wl, W.FP64)
+    for b in range(wl.plan.n_batch):
+        sub = wl.plan.sub(b)
+        o = O.Oracle(fb, sub)
+        lo, hi = int(wl.plan.offsets[b]), int(wl.plan.offsets[b + 1])
+        for c in range(hi - lo):
+            d = np.eye(hi - lo)[c] * sub.p_w[c]
+            r = o.forward_dual(d)
+            assert thr[b] == pytest.approx(r["thr"], rel=1e-11)
+            assert g[lo + c] * sub.p_w[c] == pytest.approx(r["dthr"], rel=1e-8, abs=1e-8 * abs(r["thr"]))
+
+
+def test_autograd_function():
+    t = torch()
+    from paper_2401_18022_amd.autograd import Throughput
+    wl = W.config_tiny(grid_s=16, grid_v=16, n_steps=16)
+    eng = B.Engine(wl.fibre, W.FP64)
+    model = Throughput(eng, wl.plan)
+    P = t.tensor(wl.plan.p_w * 30, dtype=t.float64, device="cuda", requires_grad=True)
+    thr, snr = model(P)
+    (2.0 * thr.sum()).backward()
+    _, _, g = gpu_grad(wl.with_plan(wl.plan.with_power(wl.plan.p_w * 30)), W.FP64)
+    np.testing.assert_allclose(P.grad.cpu().numpy(), 2.0 * g, rtol=1e-12)
