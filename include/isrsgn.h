@@ -141,7 +141,9 @@ int isrsgn_stage_times(isrsgn_fibre* h, double* ms_out, int n);
 
 /* Work done by the last forward pair-integral launch on the most recently used plan
  * (waits for it): [0] nodes evaluated (nodes on the channel support of non-empty rows),
- * [1] node-steps = nodes * n_steps, [2] tiles.  n is the capacity of out (up to 3). */
+ * [1] node-steps = nodes * n_steps, [2] tiles, [3] index of the tile-kernel variant the
+ * autotuner chose (ISRSGN_TILE_VARIANT in the environment forces one; ISRSGN_TUNE_CACHE
+ * names a file that keeps the choices across processes).  n is the capacity of out (up to 4). */
 int isrsgn_work_counts(isrsgn_fibre* h, double* out, int n);
 
 /* Frees the handle and its device memory (waits for its outstanding work).  NULL is allowed. */

@@ -57,9 +57,10 @@ __global__ void k_zero_counter2(unsigned int* c) { *c = 0u; }
 // changes -- along a row f1 and f2 move monotonically, so runs are long.  The f3 and f_i
 // contributions only touch channels k-1, k, k+1 and i: they accumulate in LDS per tile.
 struct AdjMeta {
-  int s1, s2, valid, pad;
-  float t1, t2, w3a, w3b;
-  float w3c, wi, pad2, pad3;
+  int s1, s2;
+  float t1, t2, w3a, w3b, w3c, wi;  // wi: weight of the f_i term (0 for the linear profile)
+  int valid;
+  int pad;
 };
 
 template <int kPrec>
@@ -77,7 +78,7 @@ __host__ __device__ inline size_t adjoint_lds_bytes(int nmax, int gs, int M, int
   const int mc = prec == 0 ? 16 : 8;
   const size_t rb = prec == 0 ? 4 : 8;
   return sizeof(double) * (4 * (size_t)nmax + 4 * (size_t)gs + (size_t)nmax + 4 * (size_t)M + 8) +
-         4 * (size_t)mc * 65 * rb + 4 * 64 * sizeof(AdjMeta) + 16;
+         (sizeof(StepLds) + sizeof(Col4)) * (size_t)M + 4 * (size_t)mc * 65 * rb + 4 * 64 * sizeof(AdjMeta) + 16;
 }
 
 struct AdjArgs {
@@ -107,7 +108,9 @@ __global__ void __launch_bounds__(kTileBlock) k_adjoint(AdjArgs A) {
   d += 4 * M;
   double* red = d;
   d += 8;
-  real* stage = reinterpret_cast<real*>(d);  // [4 waves][MC][65] (odd row stride: no bank conflicts)
+  StepLds* steps = reinterpret_cast<StepLds*>(d);
+  Col4* col = reinterpret_cast<Col4*>(steps + M);
+  real* stage = reinterpret_cast<real*>(col + M);  // [4 waves][MC][65] (odd row stride: no bank conflicts)
   AdjMeta* meta = reinterpret_cast<AdjMeta*>(stage + 4 * MC * 65);  // [4 waves][64]
   unsigned int* tile_slot = reinterpret_cast<unsigned int*>(meta + 4 * 64);
   const PlanView& pv = A.pv;
@@ -128,8 +131,10 @@ __global__ void __launch_bounds__(kTileBlock) k_adjoint(AdjArgs A) {
     }
     if (b != cur_b) {
       load_channels(ch, pv, A.P, o, n);
+      if (kPrec == 0) load_steps(steps, A.w.zm + (size_t)b * M, A.w.hdz32 + (size_t)b * M, M);
       cur_b = b;
     }
+    if (kPrec == 0) load_cols<kLinear>(col, A.w.lt32 + (size_t)M * o, n, M, i, k);
     for (int c = tid; c < n; c += kTileBlock) gGl[c] = 0.0;
     for (int q = tid; q < 4 * M; q += kTileBlock) tacc[q] = 0.0;
     __syncthreads();
@@ -153,10 +158,11 @@ __global__ void __launch_bounds__(kTileBlock) k_adjoint(AdjArgs A) {
         Term64 t64;
         if (valid) {
           if (kPrec == 0) {
-            t32 = term32_setup(nd, i);
+            t32 = term32_setup(nd, k, n);
             const float2* tab = A.w.lt32 + (size_t)M * o;
+#pragma unroll 4
             for (int m = 0; m < M; ++m) {
-              const float2 a = term32<kLinear>(t32, m, zm, hdz, tab, n);
+              const float2 a = term32<kLinear>(t32, m, steps, col, tab, n);
               sr += a.x;
               si += a.y;
             }
@@ -201,7 +207,7 @@ __global__ void __launch_bounds__(kTileBlock) k_adjoint(AdjArgs A) {
             real qv = 0;
             if (valid && m < M) {
               if (kPrec == 0) {
-                const float2 a = term32<kLinear>(t32, m, zm, hdz, A.w.lt32 + (size_t)M * o, n);
+                const float2 a = term32<kLinear>(t32, m, steps, col, A.w.lt32 + (size_t)M * o, n);
                 qv = (real)(cq * (sr * a.x + si * a.y));
               } else {
                 const double2 a = term64<kLinear>(t64, m, zm, dz, A.w.ell64 + (size_t)M * o, n);

@@ -12,6 +12,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -122,6 +123,7 @@ struct PlanEntry {
 }  // namespace
 
 struct isrsgn_fibre {
+  int last_variant = -1;
   isrsgn_fibre_desc desc{};
   std::vector<double> tab_f, tab_alpha, tab_aeff;
   DevBuf d_tab_f, d_tab_alpha, d_tab_aeff;
@@ -189,7 +191,7 @@ int get_plan(isrsgn_fibre* h, const isrsgn_plan* p, hipStream_t s, PlanEntry** o
     if (n > nmax) nmax = n;
   }
   if (ntiles >= (int64_t)1 << 31) return fail(ISRSGN_EINVAL, "more than 2^31 tiles in one call");
-  if (8 * (4 * (size_t)nmax + 4 * (size_t)h->desc.grid_s + 4) + 16 > 65536)
+  if (8 * (4 * (size_t)nmax + 4 * (size_t)h->desc.grid_s + 4) + 32 * (size_t)h->desc.n_steps + 16 > 65536)
     return fail(ISRSGN_EINVAL, "a plan of %d channels with grid_s %d exceeds the 64 KiB workgroup LDS", nmax,
                 h->desc.grid_s);
   const int total = p->ch_offsets[p->n_batch];
@@ -251,11 +253,93 @@ void record(isrsgn_fibre* h, int slot, hipStream_t s) {
   h->ev_used[slot] = true;
 }
 
-int tile_grid(isrsgn_fibre* h, const PlanEntry* e, bool adjoint) {
-  const int per_cu = tile_blocks_per_cu(h->fp, e->nmax, adjoint);
+int tile_grid(isrsgn_fibre* h, const PlanEntry* e, int variant, int64_t tiles) {
+  const int per_cu = tile_blocks_per_cu(h->fp, e->nmax, variant);
   int64_t g = (int64_t)per_cu * h->n_cu;
-  if (g > e->n_tiles) g = e->n_tiles;
+  if (g > tiles) g = tiles;
   return (int)(g < 1 ? 1 : g);
+}
+
+// ---------------------------------------------------------------------------- autotuner
+// The forward tile kernel comes in variants (step-loop unroll x minimum occupancy).  On the
+// first call for a discretisation the library times every variant on a slice of the real
+// tile list (the middle tiles, a few per CU) and keeps the fastest; the choice is cached per
+// process and, when ISRSGN_TUNE_CACHE names a file, across processes.  ISRSGN_TILE_VARIANT
+// forces a variant.
+struct TuneKey {
+  int prec, profile, gs, gv, M;
+  bool operator==(const TuneKey& o) const {
+    return prec == o.prec && profile == o.profile && gs == o.gs && gv == o.gv && M == o.M;
+  }
+};
+std::mutex g_tune_mu;
+std::vector<std::pair<TuneKey, int>> g_tuned;
+bool g_tune_file_read = false;
+
+void read_tune_file() {
+  if (g_tune_file_read) return;
+  g_tune_file_read = true;
+  const char* path = std::getenv("ISRSGN_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  TuneKey k;
+  int v;
+  while (std::fscanf(f, "fwd %d %d %d %d %d %d\n", &k.prec, &k.profile, &k.gs, &k.gv, &k.M, &v) == 6)
+    if (v >= 0 && v < kTileVariants) g_tuned.emplace_back(k, v);
+  std::fclose(f);
+}
+
+int pick_variant(isrsgn_fibre* h, PlanEntry* e, const double* P, const Work& w, const PlanView& pv, hipStream_t s,
+                 int* out) {
+  const char* force = std::getenv("ISRSGN_TILE_VARIANT");
+  if (force && *force) {
+    const int v = std::atoi(force);
+    *out = v >= 0 && v < kTileVariants ? v : 0;
+    return ISRSGN_OK;
+  }
+  const TuneKey key{h->desc.precision, h->desc.profile, h->desc.grid_s, h->desc.grid_v, h->desc.n_steps};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    read_tune_file();
+    for (auto& kv : g_tuned)
+      if (kv.first == key) { *out = kv.second; return ISRSGN_OK; }
+  }
+  const int64_t trial = std::min<int64_t>(e->n_tiles, std::max<int64_t>(64, 8 * (int64_t)h->n_cu));
+  const unsigned int begin = (unsigned int)((e->n_tiles - trial) / 2), end = begin + (unsigned int)trial;
+  hipEvent_t a, b;
+  hipError_t err;
+  if ((err = hipEventCreate(&a)) != hipSuccess) return hip_fail(err, "autotune events");
+  if ((err = hipEventCreate(&b)) != hipSuccess) { (void)hipEventDestroy(a); return hip_fail(err, "autotune events"); }
+  int best = 0;
+  float best_ms = 1e30f;
+  for (int v = 0; v < kTileVariants && err == hipSuccess; ++v) {
+    for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {
+      (void)hipEventRecord(a, s);
+      err = launch_tiles(pv, h->fp, P, w, e->nmax, tile_grid(h, e, v, trial), v, begin, end, s);
+      (void)hipEventRecord(b, s);
+      if (err == hipSuccess) err = hipEventSynchronize(b);
+      float ms = 0.f;
+      if (err == hipSuccess && hipEventElapsedTime(&ms, a, b) == hipSuccess && rep == 1 && ms < best_ms) {
+        best_ms = ms;
+        best = v;
+      }
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (err != hipSuccess) return hip_fail(err, "autotune");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned.emplace_back(key, best);
+  const char* path = std::getenv("ISRSGN_TUNE_CACHE");
+  if (path && *path) {
+    if (FILE* f = std::fopen(path, "a")) {
+      std::fprintf(f, "fwd %d %d %d %d %d %d\n", key.prec, key.profile, key.gs, key.gv, key.M, best);
+      std::fclose(f);
+    }
+  }
+  *out = best;
+  return ISRSGN_OK;
 }
 
 // Steps, profile, pair integrals and reduction.  Outputs may be NULL.
@@ -269,8 +353,13 @@ int forward(isrsgn_fibre* h, PlanEntry* e, const double* P, const double* nf, do
   hipError_t err;
   if ((err = launch_steps(pv, h->fp, P, w, s)) != hipSuccess) return hip_fail(err, "steps");
   if ((err = launch_profile(pv, h->fp, P, w, keep_states, s)) != hipSuccess) return hip_fail(err, "profile");
+  int variant = 0;
+  int rc = pick_variant(h, e, P, w, pv, s, &variant);
+  if (rc) return rc;
+  h->last_variant = variant;
   record(h, 1, s);
-  if ((err = launch_tiles(pv, h->fp, P, w, e->nmax, tile_grid(h, e, false), s)) != hipSuccess)
+  if ((err = launch_tiles(pv, h->fp, P, w, e->nmax, tile_grid(h, e, variant, e->n_tiles), variant, 0u,
+                          (unsigned int)e->n_tiles, s)) != hipSuccess)
     return hip_fail(err, "pair integrals");
   record(h, 2, s);
   if ((err = launch_reduce(pv, h->fp, P, nf, snr_trx, w, eta, pnli, snr, thr, s)) != hipSuccess)
@@ -462,7 +551,8 @@ int isrsgn_stage_times(isrsgn_fibre* h, double* ms, int n) {
 int isrsgn_work_counts(isrsgn_fibre* h, double* out, int n) {
   g_err.clear();
   if (!h || !out || n < 1) return fail(ISRSGN_EINVAL, "handle and output are required");
-  for (int q = 0; q < n && q < 3; ++q) out[q] = 0.0;
+  for (int q = 0; q < n && q < 4; ++q) out[q] = 0.0;
+  if (n > 3) out[3] = h->last_variant;
   if (h->plans.empty()) return ISRSGN_OK;
   const PlanEntry* e = h->plans[0].get();
   unsigned long long nodes = 0;

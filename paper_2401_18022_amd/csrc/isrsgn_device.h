@@ -334,13 +334,29 @@ __device__ inline bool make_node(const ChanLds& ch, const RowLds& rw, const Tile
 // FP32 form: the phase phi z_m is formed in FP64 and reduced to [-1/2, 1/2] revolutions before
 // the FP32 hardware sine/cosine (which take revolutions); the sinc factor uses its Taylor
 // polynomial while |phi dz_m / 2| < 1/2; E_m comes from an FP32 table of ln rho log2(e)/2.
+// Per-step data of the current plan, staged in LDS and read with uniform addresses.
+struct StepLds {
+  double zm;   // step midpoint z_m
+  float hdz;   // dz_m / 2
+  float pad;
+};
+
+// Per-tile table columns for the f3 and f_i terms of E_m, staged in LDS.  f3 lies in channel k,
+// so its interpolation segment is A = clamp(k-1) or B = clamp(k); per step:
+//   general profile: (L_A - L_i, dL_A, L_B - L_i, dL_B)   (L = ln rho log2(e)/2, dL to the next centre)
+//   linear profile:  (2 L_A, 2 dL_A, 2 L_B, 2 dL_B)
+struct Col4 {
+  float ax, ay, bx, by;
+};
+
 struct Term32 {
   double phr;
   float phrf, inv_piphr, t1, t2, t3;
-  int s1, s2, s3, ci;
+  int s1, s2;
+  bool up3;  // f3 uses segment B
 };
 
-__device__ inline Term32 term32_setup(const Node& nd, int i) {
+__device__ inline Term32 term32_setup(const Node& nd, int k, int n) {
   Term32 q;
   q.phr = nd.phr;
   q.phrf = (float)nd.phr;
@@ -350,33 +366,70 @@ __device__ inline Term32 term32_setup(const Node& nd, int i) {
   q.t3 = (float)nd.t3;
   q.s1 = nd.s1;
   q.s2 = nd.s2;
-  q.s3 = nd.s3;
-  q.ci = i;
+  const int segb = k < n - 2 ? k : (n - 2 > 0 ? n - 2 : 0);
+  q.up3 = nd.s3 == segb;
   return q;
 }
 
+// Column segments of tile (i,k): A = clamp(k-1, 0, n-2), B = clamp(k, 0, n-2).
+__device__ inline void col_segments(int k, int n, int* sa, int* sb) {
+  const int hi = n - 2 > 0 ? n - 2 : 0;
+  *sa = k - 1 < 0 ? 0 : (k - 1 > hi ? hi : k - 1);
+  *sb = k > hi ? hi : k;
+}
+
 template <bool kLinear>
-__device__ inline float2 term32(const Term32& q, int m, const double* __restrict__ zm, const float* __restrict__ hdz,
+__device__ inline void load_cols(Col4* col, const float2* __restrict__ tab, int n, int M, int i, int k) {
+  int sa, sb;
+  col_segments(k, n, &sa, &sb);
+  for (int m = threadIdx.x; m < M; m += blockDim.x) {
+    const float2* row = tab + (size_t)m * n;
+    const float2 A = row[sa], B = row[sb];
+    Col4 c;
+    if (kLinear) {
+      c.ax = 2.0f * A.x; c.ay = 2.0f * A.y; c.bx = 2.0f * B.x; c.by = 2.0f * B.y;
+    } else {
+      const float li = row[i].x;
+      c.ax = A.x - li; c.ay = A.y; c.bx = B.x - li; c.by = B.y;
+    }
+    col[m] = c;
+  }
+}
+
+__device__ inline void load_steps(StepLds* st, const double* __restrict__ zm, const float* __restrict__ hdz, int M) {
+  for (int m = threadIdx.x; m < M; m += blockDim.x) {
+    StepLds v;
+    v.zm = zm[m];
+    v.hdz = hdz[m];
+    v.pad = 0.0f;
+    st[m] = v;
+  }
+}
+
+template <bool kLinear>
+__device__ inline float2 term32(const Term32& q, int m, const StepLds* __restrict__ st, const Col4* __restrict__ col,
                                 const float2* __restrict__ tab, int n) {
-  const double tt = q.phr * zm[m];
+  const StepLds sv = st[m];
+  const Col4 cv = col[m];
+  const double tt = q.phr * sv.zm;
   const float fr = (float)(tt - rint(tt));
   const float sn = __builtin_amdgcn_sinf(fr);
   const float cs = __builtin_amdgcn_cosf(fr);
-  const float hh = q.phrf * hdz[m];
+  const float hh = q.phrf * sv.hdz;
   const float u = 2.0f * (float)kPi * hh;
   const float u2 = u * u;
-  const float dzm = 2.0f * hdz[m];
+  const float dzm = 2.0f * sv.hdz;
   const float apoly = dzm * (1.0f + u2 * (-1.0f / 6.0f + u2 * (1.0f / 120.0f - u2 * (1.0f / 5040.0f))));
   const float asn = __builtin_amdgcn_sinf(hh - rintf(hh)) * q.inv_piphr;
   const float amp0 = fabsf(u) < 0.5f ? apoly : asn;
-  const float2* row = tab + (size_t)m * n;
+  const float e3 = q.up3 ? fmaf(q.t3, cv.by, cv.bx) : fmaf(q.t3, cv.ay, cv.ax);
   float e2;
   if (kLinear) {
-    const float2 l3 = row[q.s3];
-    e2 = 2.0f * (l3.x + q.t3 * l3.y);
+    e2 = e3;
   } else {
-    const float2 l1 = row[q.s1], l2 = row[q.s2], l3 = row[q.s3];
-    e2 = (l1.x + q.t1 * l1.y) + (l2.x + q.t2 * l2.y) + (l3.x + q.t3 * l3.y) - row[q.ci].x;
+    const float2* row = tab + (size_t)m * n;
+    const float2 l1 = row[q.s1], l2 = row[q.s2];
+    e2 = fmaf(q.t1, l1.y, l1.x) + fmaf(q.t2, l2.y, l2.x) + e3;
   }
   const float amp = __builtin_amdgcn_exp2f(e2) * amp0;
   return make_float2(amp * cs, amp * sn);

@@ -10,6 +10,7 @@ namespace isrsgn {
 constexpr int kMaxChannels = 1024;  // per plan (one ODE workgroup of 1024 threads per plan)
 constexpr int kMaxGridS = 1024;     // rows per part held in LDS by the tile kernels
 constexpr int kTileBlock = 256;     // threads per tile workgroup (4 wave64)
+constexpr int kTileVariants = 6;    // forward tile-kernel variants for the autotuner
 
 // Device view of one (possibly batched) channel plan.
 struct PlanView {
@@ -67,7 +68,8 @@ hipError_t launch_steps(const PlanView& pv, const FibreParams& fp, const double*
 hipError_t launch_profile(const PlanView& pv, const FibreParams& fp, const double* P, const Work& w,
                           bool keep_states, hipStream_t s);
 hipError_t launch_tiles(const PlanView& pv, const FibreParams& fp, const double* P, const Work& w,
-                        int nmax, int grid, hipStream_t s);
+                        int nmax, int grid, int variant, unsigned int t_begin, unsigned int t_end, hipStream_t s);
+const char* tile_variant_name(int variant);
 hipError_t launch_reduce(const PlanView& pv, const FibreParams& fp, const double* P, const double* nf,
                          double snr_trx, const Work& w, double* eta, double* pnli_out, double* snr_out,
                          double* thr_out, hipStream_t s);
@@ -78,6 +80,6 @@ hipError_t launch_grad(const PlanView& pv, const FibreParams& fp, const double* 
                        hipStream_t s, hipEvent_t mid_event);
 size_t adjoint_lds(int nmax, int gs, int M, int prec);
 int adjoint_blocks_per_cu(const FibreParams& fp, int nmax);
-int tile_blocks_per_cu(const FibreParams& fp, int nmax, bool adjoint);
+int tile_blocks_per_cu(const FibreParams& fp, int nmax, int variant);
 
 }  // namespace isrsgn

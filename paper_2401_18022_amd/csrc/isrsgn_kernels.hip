@@ -171,11 +171,13 @@ struct TileArgs {
   FibreParams fp;
   const double* P;
   Work w;
-  int nmax;  // largest plan
+  int nmax;               // largest plan
+  unsigned int t_begin;   // tiles [t_begin, t_end) of the concatenated tile list
+  unsigned int t_end;
 };
 
-__host__ __device__ inline size_t tile_lds_bytes(int nmax, int gs) {
-  return sizeof(double) * (4 * (size_t)nmax + 4 * (size_t)gs + 4) + 16;
+__host__ __device__ inline size_t tile_lds_bytes(int nmax, int gs, int M) {
+  return sizeof(double) * (4 * (size_t)nmax + 4 * (size_t)gs + 4) + (sizeof(StepLds) + sizeof(Col4)) * (size_t)M + 16;
 }
 
 // Forward pair-integral kernel.  Persistent: each workgroup takes tiles (b, i, k) from a
@@ -183,8 +185,9 @@ __host__ __device__ inline size_t tile_lds_bytes(int nmax, int gs) {
 // part's grid_s x grid_v nodes across its 256 lanes (a wave covers consecutive nodes of a
 // row), accumulates node values w G1 G2 G3 |S|^2 in FP64 and reduces over the workgroup in
 // a fixed order, so results are bitwise reproducible.
-template <int kPrec, bool kLinear>
-__global__ void __launch_bounds__(kTileBlock) k_tiles(TileArgs A) {
+template <int kPrec, bool kLinear, int kUnroll, int kWaves>
+__global__ void __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(kWaves > 0 ? kWaves : 1, 8)))
+k_tiles(TileArgs A) {
   extern __shared__ __align__(16) char smem_raw[];
   const int nmax = A.nmax, GS = A.fp.grid_s, GV = A.fp.grid_v, M = A.fp.n_steps, tid = threadIdx.x;
   double* d = reinterpret_cast<double*>(smem_raw);
@@ -193,26 +196,30 @@ __global__ void __launch_bounds__(kTileBlock) k_tiles(TileArgs A) {
   const RowLds rw{d, d + GS, d + 2 * GS, d + 3 * GS};
   d += 4 * GS;
   double* red = d;
-  unsigned int* tile_slot = reinterpret_cast<unsigned int*>(d + 4);
+  d += 4;
+  StepLds* steps = reinterpret_cast<StepLds*>(d);
+  Col4* col = reinterpret_cast<Col4*>(steps + M);
+  unsigned int* tile_slot = reinterpret_cast<unsigned int*>(col + M);
   const PlanView& pv = A.pv;
   int cur_b = -1;
   for (;;) {
-    if (tid == 0) *tile_slot = atomicAdd(A.w.counter, 1u);
+    if (tid == 0) *tile_slot = A.t_begin + atomicAdd(A.w.counter, 1u);
     __syncthreads();
     const unsigned int t = *tile_slot;
-    if ((int64_t)t >= pv.n_tiles) break;
+    if (t >= A.t_end) break;
     int b, i, k;
     decode_tile(pv, t, &b, &i, &k);
     const int o = pv.off[b], n = pv.off[b + 1] - o;
-    if (b != cur_b) {
-      load_channels(ch, pv, A.P, o, n);
-      cur_b = b;
-    }
-    __syncthreads();
-    const TileGeo g = tile_geo(ch, n, i, k, A.fp.f_ref);
     const double* zm = A.w.zm + (size_t)b * M;
     const double* dz = A.w.dz + (size_t)b * M;
-    const float* hdz = A.w.hdz32 + (size_t)b * M;
+    if (b != cur_b) {
+      load_channels(ch, pv, A.P, o, n);
+      if (kPrec == 0) load_steps(steps, zm, A.w.hdz32 + (size_t)b * M, M);
+      cur_b = b;
+    }
+    if (kPrec == 0) load_cols<kLinear>(col, A.w.lt32 + (size_t)M * o, n, M, i, k);
+    __syncthreads();
+    const TileGeo g = tile_geo(ch, n, i, k, A.fp.f_ref);
     double acc = 0.0;
     unsigned int evaluated = 0;
     for (int part = kQ1; part <= kQ4; ++part) {
@@ -224,11 +231,12 @@ __global__ void __launch_bounds__(kTileBlock) k_tiles(TileArgs A) {
         if (!make_node(ch, rw, g, n, k, part, (int)(q / GV), (int)(q % GV), A.fp, &nd)) continue;
         double s2v;
         if (kPrec == 0) {
-          const Term32 tq = term32_setup(nd, i);
+          const Term32 tq = term32_setup(nd, k, n);
           const float2* tab = A.w.lt32 + (size_t)M * o;
           float sr = 0.0f, si = 0.0f;
+#pragma unroll kUnroll
           for (int m = 0; m < M; ++m) {
-            const float2 a = term32<kLinear>(tq, m, zm, hdz, tab, n);
+            const float2 a = term32<kLinear>(tq, m, steps, col, tab, n);
             sr += a.x;
             si += a.y;
           }
@@ -237,6 +245,7 @@ __global__ void __launch_bounds__(kTileBlock) k_tiles(TileArgs A) {
           const Term64 tq = term64_setup(nd, i);
           const double* tab = A.w.ell64 + (size_t)M * o;
           double sr = 0.0, si = 0.0;
+#pragma unroll kUnroll
           for (int m = 0; m < M; ++m) {
             const double2 a = term64<kLinear>(tq, m, zm, dz, tab, n);
             sr += a.x;
@@ -354,33 +363,47 @@ hipError_t launch_profile(const PlanView& pv, const FibreParams& fp, const doubl
   return e;
 }
 
-int tile_blocks_per_cu(const FibreParams& fp, int nmax, bool adjoint) {
-  (void)adjoint;
+namespace {
+
+// Tile-kernel variants (step-loop unroll, minimum waves per SIMD), chosen by the host autotuner.
+using TileKernel = void (*)(TileArgs);
+#define ISRSGN_TILE_VARIANTS(P, L)                                                                 \
+  {k_tiles<P, L, 1, 0>, k_tiles<P, L, 2, 0>, k_tiles<P, L, 4, 0>, k_tiles<P, L, 1, 4>, k_tiles<P, L, 2, 4>, \
+   k_tiles<P, L, 4, 4>}
+const TileKernel kTileKernels[2][2][kTileVariants] = {{ISRSGN_TILE_VARIANTS(0, false), ISRSGN_TILE_VARIANTS(0, true)},
+                                                     {ISRSGN_TILE_VARIANTS(1, false), ISRSGN_TILE_VARIANTS(1, true)}};
+const char* const kTileVariantNames[kTileVariants] = {"unroll1", "unroll2", "unroll4", "unroll1-w4", "unroll2-w4",
+                                                       "unroll4-w4"};
+
+TileKernel tile_kernel(const FibreParams& fp, int variant) {
+  const int v = variant < 0 || variant >= kTileVariants ? 0 : variant;
+  return kTileKernels[fp.precision ? 1 : 0][fp.profile == 0 ? 1 : 0][v];
+}
+
+}  // namespace
+
+const char* tile_variant_name(int variant) {
+  return variant >= 0 && variant < kTileVariants ? kTileVariantNames[variant] : "?";
+}
+
+int tile_blocks_per_cu(const FibreParams& fp, int nmax, int variant) {
   int nb = 0;
-  const size_t shm = tile_lds_bytes(nmax, fp.grid_s);
-  hipError_t e;
-  if (fp.precision == 0)
-    e = fp.profile == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles<0, true>, kTileBlock, shm)
-                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles<0, false>, kTileBlock, shm);
-  else
-    e = fp.profile == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles<1, true>, kTileBlock, shm)
-                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles<1, false>, kTileBlock, shm);
+  const size_t shm = tile_lds_bytes(nmax, fp.grid_s, fp.n_steps);
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(tile_kernel(fp, variant)),
+                                                              kTileBlock, shm);
   if (e != hipSuccess || nb < 1) nb = 1;
   return nb;
 }
 
 hipError_t launch_tiles(const PlanView& pv, const FibreParams& fp, const double* P, const Work& w, int nmax,
-                        int grid, hipStream_t s) {
+                        int grid, int variant, unsigned int t_begin, unsigned int t_end, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, w.counter, w.nodes);
-  TileArgs a{pv, fp, P, w, nmax};
-  const size_t shm = tile_lds_bytes(nmax, fp.grid_s);
-  if (fp.precision == 0) {
-    if (fp.profile == 0) hipLaunchKernelGGL((k_tiles<0, true>), dim3(grid), dim3(kTileBlock), shm, s, a);
-    else hipLaunchKernelGGL((k_tiles<0, false>), dim3(grid), dim3(kTileBlock), shm, s, a);
-  } else {
-    if (fp.profile == 0) hipLaunchKernelGGL((k_tiles<1, true>), dim3(grid), dim3(kTileBlock), shm, s, a);
-    else hipLaunchKernelGGL((k_tiles<1, false>), dim3(grid), dim3(kTileBlock), shm, s, a);
-  }
+  TileArgs a{pv, fp, P, w, nmax, t_begin, t_end};
+  const size_t shm = tile_lds_bytes(nmax, fp.grid_s, fp.n_steps);
+  void* args[] = {&a};
+  hipError_t e = hipLaunchKernel(reinterpret_cast<const void*>(tile_kernel(fp, variant)), dim3(grid),
+                                 dim3(kTileBlock), args, shm, s);
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 
