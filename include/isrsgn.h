@@ -131,6 +131,14 @@ int isrsgn_snr_grad(isrsgn_fibre* h, const isrsgn_plan* plan, const double* P_w_
 int isrsgn_profile(isrsgn_fibre* h, const isrsgn_plan* plan, const double* P_w_dev, double* z_mid_dev,
                    double* dz_dev, double* ell_dev, double* ell_L_dev, void* hip_stream);
 
+/* Graph mode (a9).  When enabled, each (plan, entry point, transceiver SNR) is captured once
+ * into a HIP graph on the handle's own non-blocking stream, over device buffers the plan
+ * owns; every later call copies P and NF in with a kernel, launches the graph on the
+ * caller's stream and copies the outputs out (no memset or memcpy nodes).  The first call
+ * for a discretisation runs eagerly so the autotuner can time the tile-kernel variants.
+ * Results are identical to eager calls.  Stage timers report only the whole call. */
+int isrsgn_set_graph(isrsgn_fibre* h, int enabled);
+
 /* Stage timers.  When enabled, every call records HIP events around its stages on
  * its stream.  isrsgn_stage_times waits for the last call and writes milliseconds
  * for: [0] steps+profile, [1] pair integrals (forward tile kernel), [2] reduction,

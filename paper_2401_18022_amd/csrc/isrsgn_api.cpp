@@ -68,6 +68,12 @@ uint64_t fnv1a(const void* data, size_t n, uint64_t h) {
   return h;
 }
 
+struct GraphEntry {
+  int kind;
+  double snr_trx;
+  hipGraphExec_t exec;
+};
+
 // A validated channel plan resident on the device, with its workspace.
 struct PlanEntry {
   uint64_t key = 0;
@@ -80,6 +86,12 @@ struct PlanEntry {
   DevBuf abar, zm, dz, hdz32, ell64, lt32, ellL, tiles, pnli, snr, counter;
   DevBuf states, state_off, lam, gG, gL, gLL, gP, coef;
   bool grad_ready = false;
+  // graph mode: owned inputs/outputs and the instantiated graphs
+  DevBuf g_P, g_nf, g_a, g_b, g_c, g_thr;
+  std::vector<GraphEntry> graphs;
+  ~PlanEntry() {
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+  }
   PlanView view() const {
     PlanView v;
     v.n_batch = n_batch;
@@ -124,6 +136,8 @@ struct PlanEntry {
 
 struct isrsgn_fibre {
   int last_variant = -1;
+  bool graph = false;
+  hipStream_t cap_stream = nullptr;
   isrsgn_fibre_desc desc{};
   std::vector<double> tab_f, tab_alpha, tab_aeff;
   DevBuf d_tab_f, d_tab_alpha, d_tab_aeff;
@@ -368,6 +382,132 @@ int forward(isrsgn_fibre* h, PlanEntry* e, const double* P, const double* nf, do
   return ISRSGN_OK;
 }
 
+enum { kEta = 0, kSnr = 1, kGrad = 2 };
+
+int ensure_grad_workspace(isrsgn_fibre* h, PlanEntry* e) {
+  const int M = h->desc.n_steps;
+  if (adjoint_lds(e->nmax, h->desc.grid_s, M, h->desc.precision) > 65536)
+    return fail(ISRSGN_EUNSUPPORTED, "the adjoint of a %d-channel plan with grid_s %d and %d steps exceeds 64 KiB LDS",
+                e->nmax, h->desc.grid_s, M);
+  if (e->grad_ready) return ISRSGN_OK;
+  const size_t nt = (size_t)e->n_total, nb = (size_t)e->n_batch;
+  std::vector<int64_t> soff(nb + 1, 0);
+  const bool ode = h->desc.profile == ISRSGN_PROFILE_ODE;
+  for (size_t b = 0; b < nb; ++b) {
+    const int64_t n = e->off[b + 1] - e->off[b];
+    soff[b + 1] = soff[b] + (ode ? ((int64_t)M * 2 * h->desc.ode_sub + 1) * n : 0);
+  }
+  bool ok = e->lam.ensure(8 * nt) && e->gG.ensure(8 * nt) && e->gL.ensure(8 * nt * M) && e->gLL.ensure(8 * nt) &&
+            e->gP.ensure(8 * nt) && e->coef.ensure(8 * 8 * nb * (M + 1)) && e->state_off.ensure(8 * (nb + 1)) &&
+            e->states.ensure(8 * (size_t)soff[nb]);
+  if (!ok) return fail(ISRSGN_ENOMEM, "device allocation failed for the adjoint workspace");
+  hipError_t err = hipMemcpy(e->state_off.p, soff.data(), 8 * (nb + 1), hipMemcpyHostToDevice);
+  if (err != hipSuccess) return hip_fail(err, "state offsets");
+  e->grad_ready = true;
+  return ISRSGN_OK;
+}
+
+// The whole sequence of one call, enqueued on s.
+int enqueue_call(isrsgn_fibre* h, PlanEntry* e, int kind, const double* P, const double* nf, double snr_trx,
+                 double* eta, double* pnli, double* tiles, double* snr, double* thr, double* dthr, hipStream_t s) {
+  int rc = forward(h, e, P, nf, snr_trx, eta, pnli, tiles, snr, thr,
+                   kind == kGrad && h->desc.profile == ISRSGN_PROFILE_ODE, s);
+  if (rc || kind != kGrad) return rc;
+  const int per_cu = adjoint_blocks_per_cu(h->fp, e->nmax);
+  int64_t grid = (int64_t)per_cu * h->n_cu;
+  if (grid > e->n_tiles) grid = e->n_tiles;
+  hipEvent_t mid = (h->timing && h->ev_ready) ? h->ev[4] : nullptr;
+  if (mid) h->ev_used[4] = true;
+  hipError_t err = launch_grad(e->view(), h->fp, P, nf, snr_trx, e->work(), e->nmax, (int)(grid < 1 ? 1 : grid),
+                               e->coef.as<double>(), dthr, s, mid);
+  if (err != hipSuccess) return hip_fail(err, "adjoint");
+  record(h, 5, s);
+  return ISRSGN_OK;
+}
+
+bool variant_known(isrsgn_fibre* h) {
+  const char* force = std::getenv("ISRSGN_TILE_VARIANT");
+  if (force && *force) return true;
+  const TuneKey key{h->desc.precision, h->desc.profile, h->desc.grid_s, h->desc.grid_v, h->desc.n_steps};
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  read_tune_file();
+  for (auto& kv : g_tuned)
+    if (kv.first == key) return true;
+  return false;
+}
+
+// Graph mode: the call's kernels are captured once per (plan, kind, transceiver SNR) on the
+// handle's capture stream, working on buffers the plan owns; each call then copies the inputs
+// in, launches the graph on the caller's stream and copies the outputs out (all kernels: no
+// memset or memcpy nodes).
+int run_graph(isrsgn_fibre* h, PlanEntry* e, int kind, const double* P, const double* nf, double snr_trx,
+              double* eta, double* pnli, double* tiles, double* snr, double* thr, double* dthr, hipStream_t s) {
+  const size_t nt = (size_t)e->n_total, nb = (size_t)e->n_batch;
+  if (!e->g_P.ensure(8 * nt) || !e->g_nf.ensure(8 * nt) || !e->g_a.ensure(8 * nt) || !e->g_b.ensure(8 * nt) ||
+      !e->g_c.ensure(8 * std::max(nt, nb)) || !e->g_thr.ensure(8 * nb))
+    return fail(ISRSGN_ENOMEM, "device allocation failed for the graph buffers");
+  GraphEntry* ge = nullptr;
+  for (auto& g : e->graphs)
+    if (g.kind == kind && g.snr_trx == snr_trx) ge = &g;
+  double* o_a = e->g_a.as<double>();  // eta | snr
+  double* o_b = e->g_b.as<double>();  // pnli | dthr
+  double* o_t = e->g_thr.as<double>();
+  if (!ge) {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const bool timing = h->timing;
+    h->timing = false;
+    hipError_t err = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (err != hipSuccess) { h->timing = timing; return hip_fail(err, "hipStreamBeginCapture"); }
+    int rc;
+    if (kind == kEta)
+      rc = enqueue_call(h, e, kind, e->g_P.as<double>(), nullptr, 0.0, o_a, o_b, nullptr, nullptr, nullptr, nullptr,
+                        h->cap_stream);
+    else
+      rc = enqueue_call(h, e, kind, e->g_P.as<double>(), e->g_nf.as<double>(), snr_trx, nullptr, nullptr, nullptr,
+                        o_a, o_t, kind == kGrad ? o_b : nullptr, h->cap_stream);
+    err = hipStreamEndCapture(h->cap_stream, &graph);
+    h->timing = timing;
+    if (rc) { if (graph) (void)hipGraphDestroy(graph); return rc; }
+    if (err != hipSuccess) return hip_fail(err, "hipStreamEndCapture");
+    err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (err != hipSuccess) return hip_fail(err, "hipGraphInstantiate");
+    e->graphs.push_back(GraphEntry{kind, snr_trx, exec});
+    ge = &e->graphs.back();
+  }
+  for (int q = 0; q < 7; ++q) h->ev_used[q] = false;
+  record(h, 0, s);
+  hipError_t err = launch_copy(e->g_P.as<double>(), P, (int64_t)nt, s);
+  if (err == hipSuccess && nf) err = launch_copy(e->g_nf.as<double>(), nf, (int64_t)nt, s);
+  if (err == hipSuccess) err = hipGraphLaunch(ge->exec, s);
+  if (err == hipSuccess) {
+    if (kind == kEta) {
+      err = launch_copy(eta, o_a, (int64_t)nt, s);
+      if (err == hipSuccess && pnli) err = launch_copy(pnli, o_b, (int64_t)nt, s);
+      if (err == hipSuccess && tiles) err = launch_copy(tiles, e->tiles.as<double>(), e->n_tiles, s);
+    } else {
+      err = launch_copy(snr, o_a, (int64_t)nt, s);
+      if (err == hipSuccess) err = launch_copy(thr, o_t, (int64_t)nb, s);
+      if (err == hipSuccess && kind == kGrad) err = launch_copy(dthr, o_b, (int64_t)nt, s);
+    }
+  }
+  if (err != hipSuccess) return hip_fail(err, "graph launch");
+  record(h, 5, s);
+  return ISRSGN_OK;
+}
+
+int run_call(isrsgn_fibre* h, const isrsgn_plan* plan, int kind, const double* P, const double* nf, double snr_trx,
+             double* eta, double* pnli, double* tiles, double* snr, double* thr, double* dthr, hipStream_t s) {
+  PlanEntry* e;
+  int rc = get_plan(h, plan, s, &e);
+  if (rc) return rc;
+  if (kind == kGrad && (rc = ensure_grad_workspace(h, e))) return rc;
+  if (h->graph && variant_known(h))
+    return run_graph(h, e, kind, P, nf, snr_trx, eta, pnli, tiles, snr, thr, dthr, s);
+  return enqueue_call(h, e, kind, P, nf, snr_trx, eta, pnli, tiles, snr, thr, dthr, s);
+}
+
 }  // namespace
 
 extern "C" {
@@ -433,11 +573,8 @@ int isrsgn_eta(isrsgn_fibre* h, const isrsgn_plan* plan, const double* P, double
                void* stream) {
   g_err.clear();
   if (!h || !P || !eta) return fail(ISRSGN_EINVAL, "handle, P_w_dev and eta_dev are required");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  PlanEntry* e;
-  int rc = get_plan(h, plan, s, &e);
-  if (rc) return rc;
-  return forward(h, e, P, nullptr, 0.0, eta, pnli, tiles, nullptr, nullptr, false, s);
+  return run_call(h, plan, kEta, P, nullptr, 0.0, eta, pnli, tiles, nullptr, nullptr, nullptr,
+                  static_cast<hipStream_t>(stream));
 }
 
 int isrsgn_snr(isrsgn_fibre* h, const isrsgn_plan* plan, const double* P, const double* nf, double snr_trx,
@@ -445,11 +582,8 @@ int isrsgn_snr(isrsgn_fibre* h, const isrsgn_plan* plan, const double* P, const 
   g_err.clear();
   if (!h || !P || !nf || !snr || !thr) return fail(ISRSGN_EINVAL, "handle, P, NF, snr and thr pointers are required");
   if (!(snr_trx >= 0) || !is_fin(snr_trx)) return fail(ISRSGN_EINVAL, "snr_trx_lin must be finite and >= 0");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  PlanEntry* e;
-  int rc = get_plan(h, plan, s, &e);
-  if (rc) return rc;
-  return forward(h, e, P, nf, snr_trx, nullptr, nullptr, nullptr, snr, thr, false, s);
+  return run_call(h, plan, kSnr, P, nf, snr_trx, nullptr, nullptr, nullptr, snr, thr, nullptr,
+                  static_cast<hipStream_t>(stream));
 }
 
 int isrsgn_snr_grad(isrsgn_fibre* h, const isrsgn_plan* plan, const double* P, const double* nf, double snr_trx,
@@ -458,41 +592,18 @@ int isrsgn_snr_grad(isrsgn_fibre* h, const isrsgn_plan* plan, const double* P, c
   if (!h || !P || !nf || !snr || !thr || !dthr)
     return fail(ISRSGN_EINVAL, "handle, P, NF, snr, thr and dthr pointers are required");
   if (!(snr_trx >= 0) || !is_fin(snr_trx)) return fail(ISRSGN_EINVAL, "snr_trx_lin must be finite and >= 0");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  PlanEntry* e;
-  int rc = get_plan(h, plan, s, &e);
-  if (rc) return rc;
-  const int M = h->desc.n_steps;
-  if (adjoint_lds(e->nmax, h->desc.grid_s, M, h->desc.precision) > 65536)
-    return fail(ISRSGN_EUNSUPPORTED, "the adjoint of a %d-channel plan with grid_s %d and %d steps exceeds 64 KiB LDS",
-                e->nmax, h->desc.grid_s, M);
-  if (!e->grad_ready) {
-    const size_t nt = (size_t)e->n_total, nb = (size_t)e->n_batch;
-    std::vector<int64_t> soff(nb + 1, 0);
-    const bool ode = h->desc.profile == ISRSGN_PROFILE_ODE;
-    for (size_t b = 0; b < nb; ++b) {
-      const int64_t n = e->off[b + 1] - e->off[b];
-      soff[b + 1] = soff[b] + (ode ? ((int64_t)M * 2 * h->desc.ode_sub + 1) * n : 0);
-    }
-    bool ok = e->lam.ensure(8 * nt) && e->gG.ensure(8 * nt) && e->gL.ensure(8 * nt * M) && e->gLL.ensure(8 * nt) &&
-              e->gP.ensure(8 * nt) && e->coef.ensure(8 * 8 * nb * (M + 1)) && e->state_off.ensure(8 * (nb + 1)) &&
-              e->states.ensure(8 * (size_t)soff[nb]);
-    if (!ok) return fail(ISRSGN_ENOMEM, "device allocation failed for the adjoint workspace");
-    hipError_t err = hipMemcpy(e->state_off.p, soff.data(), 8 * (nb + 1), hipMemcpyHostToDevice);
-    if (err != hipSuccess) return hip_fail(err, "state offsets");
-    e->grad_ready = true;
+  return run_call(h, plan, kGrad, P, nf, snr_trx, nullptr, nullptr, nullptr, snr, thr, dthr,
+                  static_cast<hipStream_t>(stream));
+}
+
+int isrsgn_set_graph(isrsgn_fibre* h, int enabled) {
+  g_err.clear();
+  if (!h) return fail(ISRSGN_EINVAL, "handle is NULL");
+  if (enabled && !h->cap_stream) {
+    hipError_t err = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
+    if (err != hipSuccess) return hip_fail(err, "capture stream");
   }
-  rc = forward(h, e, P, nf, snr_trx, nullptr, nullptr, nullptr, snr, thr, h->desc.profile == ISRSGN_PROFILE_ODE, s);
-  if (rc) return rc;
-  const int per_cu = adjoint_blocks_per_cu(h->fp, e->nmax);
-  int64_t grid = (int64_t)per_cu * h->n_cu;
-  if (grid > e->n_tiles) grid = e->n_tiles;
-  hipEvent_t mid = (h->timing && h->ev_ready) ? h->ev[4] : nullptr;
-  if (mid) h->ev_used[4] = true;
-  hipError_t err = launch_grad(e->view(), h->fp, P, nf, snr_trx, e->work(), e->nmax, (int)(grid < 1 ? 1 : grid),
-                               e->coef.as<double>(), dthr, s, mid);
-  if (err != hipSuccess) return hip_fail(err, "adjoint");
-  record(h, 5, s);
+  h->graph = enabled != 0;
   return ISRSGN_OK;
 }
 
@@ -568,6 +679,8 @@ void isrsgn_destroy(isrsgn_fibre* h) {
   (void)hipDeviceSynchronize();
   if (h->ev_ready)
     for (int q = 0; q < 7; ++q) (void)hipEventDestroy(h->ev[q]);
+  h->plans.clear();
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   delete h;
 }
 

@@ -81,5 +81,6 @@ hipError_t launch_grad(const PlanView& pv, const FibreParams& fp, const double* 
 size_t adjoint_lds(int nmax, int gs, int M, int prec);
 int adjoint_blocks_per_cu(const FibreParams& fp, int nmax);
 int tile_blocks_per_cu(const FibreParams& fp, int nmax, int variant);
+hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
 
 }  // namespace isrsgn

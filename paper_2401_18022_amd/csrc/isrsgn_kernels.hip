@@ -314,6 +314,11 @@ __global__ void k_throughput(PlanView pv, const double* __restrict__ P, Work w, 
   if (threadIdx.x == 0) thr[b] = s;
 }
 
+__global__ void k_copy(double* __restrict__ dst, const double* __restrict__ src, int64_t n) {
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+    dst[q] = src[q];
+}
+
 __global__ void k_copy_profile(PlanView pv, FibreParams fp, Work w, double* zm, double* dz, double* ell,
                                double* ellL) {
   const int M = fp.n_steps;
@@ -416,6 +421,12 @@ hipError_t launch_reduce(const PlanView& pv, const FibreParams& fp, const double
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !thr_out) return e;
   hipLaunchKernelGGL(k_throughput, dim3(pv.n_batch), dim3(256), 0, s, pv, P, w, thr_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s) {
+  const int64_t blocks = (n + 255) / 256 < 2048 ? (n + 255) / 256 : 2048;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)(blocks < 1 ? 1 : blocks)), dim3(256), 0, s, dst, src, n);
   return hipGetLastError();
 }
 

@@ -92,3 +92,24 @@ def test_product_path_does_not_import_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 for bad in ("import oracle", "from oracle", "liboracle", "orc_"):
                     assert bad not in text, (f, bad)
+
+
+def test_segment_counts_reproduce_table2():
+    """N_B = round(B_band / B_p), B_band = channels x 100 GHz, B_p = 750 GHz (O) / 1.5 THz (Sec. IV):
+    the paper's channel counts give its segment counts (Table II)."""
+    import json
+    from paper_2401_18022_amd import optimise
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "table2_noise_figure.json")))
+    assert optimise.segment_counts(g["channels"]) == g["segments"]
+    assert sum(g["segments"]) == 49
+
+
+def test_segment_matrix_interpolates():
+    from paper_2401_18022_amd import optimise
+    f = W.ou_grid()
+    A, counts = optimise.segment_matrix(f)
+    np.testing.assert_allclose(A.sum(1), 1.0, rtol=1e-12)    # partition of unity per channel
+    x = np.linspace(-5, 5, A.shape[1])
+    p = A @ x
+    assert p.min() >= -5 - 1e-12 and p.max() <= 5 + 1e-12
+    assert A.shape == (589, sum(counts)) and all(c >= 2 for c in counts)

@@ -1,0 +1,90 @@
+"""Batching (many plans of uneven size in one persistent launch), graph mode and the tile-kernel
+autotuner, all checked against eager single calls or the oracle."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2401_18022_amd import binding as B
+from paper_2401_18022_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+def test_graph_replays_match_eager():
+    """Each replay of a captured call, with eager torch work and synchronisations between replays,
+    equals the eager result bit for bit."""
+    t = torch()
+    plans = [W.random_small(n, seed=80 + n).plan for n in (7, 3, 12)]
+    fb = W.random_small(7, seed=87, grid_s=16, grid_v=16, n_steps=20).fibre
+    plan = W.concat_plans(plans)
+    P = t.tensor(plan.p_w * 20, dtype=t.float64, device="cuda")
+    nf = t.tensor(plan.nf_lin, dtype=t.float64, device="cuda")
+    ref = B.Engine(fb, W.FP32)
+    snr0, thr0, g0 = ref.snr_grad(plan, P, nf, 50.0)
+    eta0, pnli0, tl0 = ref.eta(plan, P, tiles=True)
+    eng = B.Engine(fb, W.FP32)
+    eng.set_graph(True)
+    for rep in range(4):
+        noise = t.randn(1000, device="cuda").sum()   # eager work between replays
+        snr, thr, g = eng.snr_grad(plan, P, nf, 50.0)
+        eta, pnli, tl = eng.eta(plan, P, tiles=True)
+        t.cuda.synchronize()
+        assert t.equal(snr, snr0) and t.equal(thr, thr0) and t.equal(g, g0), rep
+        assert t.equal(eta, eta0) and t.equal(pnli, pnli0) and t.equal(tl, tl0), rep
+        assert t.isfinite(noise)
+    # new input values flow through the copy-in of the same graph
+    P2 = P * 1.7
+    snr2, thr2, g2 = eng.snr_grad(plan, P2, nf, 50.0)
+    snr2e, thr2e, g2e = ref.snr_grad(plan, P2, nf, 50.0)
+    t.cuda.synchronize()
+    assert t.equal(thr2, thr2e) and t.equal(g2, g2e)
+
+
+def test_every_tile_variant_agrees():
+    """All autotuner candidates compute the same tiles (same arithmetic, different scheduling)."""
+    t = torch()
+    wl = W.random_small(9, seed=3, grid_s=24, grid_v=40, n_steps=30)
+    P = t.tensor(wl.plan.p_w, dtype=t.float64, device="cuda")
+    out = []
+    try:
+        for v in range(6):
+            os.environ["ISRSGN_TILE_VARIANT"] = str(v)
+            eng = B.Engine(wl.fibre, W.FP32)
+            _, _, tl = eng.eta(wl.plan, P, tiles=True)
+            out.append(tl.cpu().numpy())
+            assert eng.work_counts()["variant"] == v
+    finally:
+        del os.environ["ISRSGN_TILE_VARIANT"]
+    for v in range(1, 6):
+        np.testing.assert_allclose(out[v], out[0], rtol=1e-6)
+
+
+def test_batch_workload_sample_matches_oracle():
+    """Eight profiles of the seeded batch workload (uneven sub-bands of the O-to-U grid) at a
+    reduced grid, in one launch: three tile rows per profile against the oracle."""
+    t = torch()
+    wl = W.config_batch(n_profiles=8, grid_s=12, grid_v=12, n_steps=16)
+    eng = B.Engine(wl.fibre, W.FP32)
+    P = t.tensor(wl.plan.p_w, dtype=t.float64, device="cuda")
+    nf = t.tensor(wl.plan.nf_lin, dtype=t.float64, device="cuda")
+    eta, pnli, tl = eng.eta(wl.plan, P, tiles=True)
+    snr, thr = eng.snr(wl.plan, P, nf)
+    t.cuda.synchronize()
+    blocks = B.tiles_to_blocks(tl, wl.plan)
+    for b in range(wl.plan.n_batch):
+        sub = wl.plan.sub(b)
+        n = len(sub.f_hz)
+        coi = [0, n // 2, n - 1]
+        print(f"[batch] plan {b} n={n}", flush=True)
+        r = O.Oracle(wl.fibre, sub).forward(coi)
+        np.testing.assert_allclose(blocks[b][coi], r["tiles"], rtol=2e-6)
+        lo = int(wl.plan.offsets[b])
+        np.testing.assert_allclose(snr.cpu().numpy()[lo + np.array(coi)], r["snr"], rtol=2e-6)

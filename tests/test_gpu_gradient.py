@@ -127,3 +127,31 @@ def test_autograd_function():
     (2.0 * thr.sum()).backward()
     _, _, g = gpu_grad(wl.with_plan(wl.plan.with_power(wl.plan.p_w * 30)), W.FP64)
     np.testing.assert_allclose(P.grad.cpu().numpy(), 2.0 * g, rtol=1e-12)
+
+
+def test_launch_power_optimisation_improves_and_rechecks():
+    """Gradient ascent in dBm with the adjoint (Sec. IV, bounds +-5 dBm) raises the throughput;
+    the optimised powers are re-checked against the FP64 oracle on seeded channels."""
+    from paper_2401_18022_amd.autograd import optimise_launch_power
+    wl = W.config_cl(grid_s=12, grid_v=12, n_steps=24)
+    eng = B.Engine(wl.fibre, W.FP32)
+    p0 = 10 * np.log10(wl.plan.p_w / 1e-3)
+    p, hist = optimise_launch_power(eng, wl.plan, p0, steps=8, lr_db=0.3)
+    assert hist[-1] > hist[0]
+    assert np.all(p >= -5.0) and np.all(p <= 5.0)
+    plan = wl.plan.with_power(1e-3 * 10 ** (p / 10))
+    t = torch()
+    snr, thr = eng.snr(plan, t.tensor(plan.p_w, dtype=t.float64, device="cuda"),
+                       t.tensor(plan.nf_lin, dtype=t.float64, device="cuda"))
+    coi = W.fd_channels(n_ch=95, count=6)
+    r = O.Oracle(wl.fibre, plan).forward(coi)
+    d = np.abs(10 * np.log10(snr.cpu().numpy()[coi] / r["snr"]))
+    assert d.max() <= 0.01
+
+
+def test_segment_lbfgsb_runs_a_few_iterations():
+    from paper_2401_18022_amd import optimise
+    wl = W.config_ou(grid_s=8, grid_v=8, n_steps=12)
+    eng = B.Engine(wl.fibre, W.FP32)
+    x, p, hist, res, counts = optimise.segment_lbfgsb(eng, wl.plan, maxiter=3)
+    assert len(x) == sum(counts) and max(hist) > hist[0]
