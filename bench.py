@@ -101,12 +101,11 @@ def main():
     ms_step = 1e3 * elapsed / args.steps
     tiles_ms = stages["tiles"] / args.steps
     node_steps = work["node_steps"]
-    achieved = node_steps * SLOTS_PER_NODE_STEP * FLOP_EQ_PER_SLOT / (tiles_ms * 1e-3) / 1e12
-    dominant = "pair_integral_forward"
-    dom_ms = tiles_ms
+    # the adjoint sweeps every node's steps twice (S, then each term's share of dT/dE_m)
+    dominant, dom_ms, dom_sweeps = "pair_integral_forward", tiles_ms, 1
     if grad and stages["adjoint_tiles"] / args.steps > tiles_ms:
-        dominant = "pair_integral_adjoint"
-        dom_ms = stages["adjoint_tiles"] / args.steps
+        dominant, dom_ms, dom_sweeps = "pair_integral_adjoint", stages["adjoint_tiles"] / args.steps, 2
+    achieved = dom_sweeps * node_steps * SLOTS_PER_NODE_STEP * FLOP_EQ_PER_SLOT / (dom_ms * 1e-3) / 1e12
 
     fp64 = None
     if not args.no_fp64:
@@ -153,10 +152,11 @@ def main():
                    "pairs_per_step": n * n, "grad": bool(grad)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None, "kernel": dominant,
-                     "kernel_ms": dom_ms, "node_steps_per_launch": node_steps,
-                     "slots_per_node_step": SLOTS_PER_NODE_STEP},
+                     "kernel_ms": dom_ms, "node_steps_per_launch": dom_sweeps * node_steps,
+                     "slots_per_node_step": SLOTS_PER_NODE_STEP, "tile_variant": work["variant"]},
         "cpu_baseline": cpu,
         "stages_ms": {k: v / args.steps for k, v in stages.items()},
+        "snr_wall_ms": (stages["profile"] + stages["tiles"] + stages["reduce"]) / args.steps,
         "node_steps_per_s": node_steps / (tiles_ms * 1e-3),
         "throughput_tbps": thr / 1e12,
         "fp64_form": fp64,

@@ -17,6 +17,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libisrsgn.so")
+PEAKS = os.path.join(PKG, "isrsgn_peaks")
 SOURCES = ["isrsgn_kernels.hip", "isrsgn_adjoint.hip", "isrsgn_api.cpp"]
 ARCH = os.environ.get("ISRSGN_ARCH", "gfx950")
 
@@ -60,6 +61,16 @@ def build(verbose: bool = False) -> str:
             raise RuntimeError("link of libisrsgn.so failed")
         shutil.copyfile(out_tmp, LIB + ".tmp")
         os.replace(LIB + ".tmp", LIB)
+        # the VALU peak / accuracy microbenchmark used for the roofline
+        exe_tmp = os.path.join(tmp, "isrsgn_peaks")
+        cmd = [cc, *HIPCC_FLAGS, "-x", "hip", os.path.join(CSRC, "peaks.hip"), "-o", exe_tmp]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError("build of isrsgn_peaks failed")
+        shutil.copyfile(exe_tmp, PEAKS + ".tmp")
+        os.chmod(PEAKS + ".tmp", 0o755)
+        os.replace(PEAKS + ".tmp", PEAKS)
     return LIB
 
 

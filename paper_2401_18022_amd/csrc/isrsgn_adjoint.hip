@@ -156,16 +156,21 @@ __global__ void __launch_bounds__(kTileBlock) k_adjoint(AdjArgs A) {
         real sr = 0, si = 0;
         Term32 t32;
         Term64 t64;
+        bool tsmall = true, tlarge = true;  // invalid lanes do not restrict the wave's tier
+        if (valid && kPrec == 0) {
+          t32 = term32_setup(nd, k, n);
+          node_tier_flags(t32, steps, M, &tsmall, &tlarge);
+        }
+        const int tier = wave_tier(tsmall, tlarge);
         if (valid) {
           if (kPrec == 0) {
-            t32 = term32_setup(nd, k, n);
             const float2* tab = A.w.lt32 + (size_t)M * o;
-#pragma unroll 4
-            for (int m = 0; m < M; ++m) {
-              const float2 a = term32<kLinear>(t32, m, steps, col, tab, n);
-              sr += a.x;
-              si += a.y;
-            }
+            float a32, b32;
+            if (tier == kTierSmall) accumulate32<kLinear, kTierSmall, 4>(t32, steps, col, tab, n, M, &a32, &b32);
+            else if (tier == kTierLarge) accumulate32<kLinear, kTierLarge, 4>(t32, steps, col, tab, n, M, &a32, &b32);
+            else accumulate32<kLinear, kTierMixed, 4>(t32, steps, col, tab, n, M, &a32, &b32);
+            sr = a32;
+            si = b32;
           } else {
             t64 = term64_setup(nd, i);
             const double* tab = A.w.ell64 + (size_t)M * o;
@@ -207,7 +212,7 @@ __global__ void __launch_bounds__(kTileBlock) k_adjoint(AdjArgs A) {
             real qv = 0;
             if (valid && m < M) {
               if (kPrec == 0) {
-                const float2 a = term32<kLinear>(t32, m, steps, col, A.w.lt32 + (size_t)M * o, n);
+                const float2 a = term32_tier<kLinear>(tier, t32, m, steps, col, A.w.lt32 + (size_t)M * o, n);
                 qv = (real)(cq * (sr * a.x + si * a.y));
               } else {
                 const double2 a = term64<kLinear>(t64, m, zm, dz, A.w.ell64 + (size_t)M * o, n);

@@ -338,7 +338,7 @@ __device__ inline bool make_node(const ChanLds& ch, const RowLds& rw, const Tile
 struct StepLds {
   double zm;   // step midpoint z_m
   float hdz;   // dz_m / 2
-  float pad;
+  float zmf;   // z_m in FP32 (small-phase tier)
 };
 
 // Per-tile table columns for the f3 and f_i terms of E_m, staged in LDS.  f3 lies in channel k,
@@ -401,27 +401,45 @@ __device__ inline void load_steps(StepLds* st, const double* __restrict__ zm, co
     StepLds v;
     v.zm = zm[m];
     v.hdz = hdz[m];
-    v.pad = 0.0f;
+    v.zmf = (float)zm[m];
     st[m] = v;
   }
 }
 
-template <bool kLinear>
+// Accuracy tiers of the FP32 step term, chosen per wave (all its lanes must qualify):
+//   kTierSmall: |phi| z_max < 1/4 revolution and |phi dz_m / 2| < 1/2 at every step: the phase
+//               is formed in FP32 (error < 5e-8 revolutions) and the sinc factor is its Taylor
+//               polynomial -- no FP64 and one transcendental fewer;
+//   kTierLarge: |phi dz_m / 2| >= 1/2 at every step: FP64 phase, sinc from the hardware sine;
+//   kTierMixed: FP64 phase, polynomial or sine chosen per step.
+enum { kTierMixed = 0, kTierSmall = 1, kTierLarge = 2 };
+
+template <bool kLinear, int kTier>
 __device__ inline float2 term32(const Term32& q, int m, const StepLds* __restrict__ st, const Col4* __restrict__ col,
                                 const float2* __restrict__ tab, int n) {
   const StepLds sv = st[m];
   const Col4 cv = col[m];
-  const double tt = q.phr * sv.zm;
-  const float fr = (float)(tt - rint(tt));
+  float fr;
+  if (kTier == kTierSmall) {
+    const float tt = q.phrf * sv.zmf;
+    fr = tt - rintf(tt);
+  } else {
+    const double tt = q.phr * sv.zm;
+    fr = (float)(tt - rint(tt));
+  }
   const float sn = __builtin_amdgcn_sinf(fr);
   const float cs = __builtin_amdgcn_cosf(fr);
   const float hh = q.phrf * sv.hdz;
-  const float u = 2.0f * (float)kPi * hh;
-  const float u2 = u * u;
-  const float dzm = 2.0f * sv.hdz;
-  const float apoly = dzm * (1.0f + u2 * (-1.0f / 6.0f + u2 * (1.0f / 120.0f - u2 * (1.0f / 5040.0f))));
-  const float asn = __builtin_amdgcn_sinf(hh - rintf(hh)) * q.inv_piphr;
-  const float amp0 = fabsf(u) < 0.5f ? apoly : asn;
+  float amp0;
+  if (kTier != kTierLarge) {
+    const float u = 2.0f * (float)kPi * hh;
+    const float u2 = u * u;
+    const float dzm = 2.0f * sv.hdz;
+    amp0 = dzm * (1.0f + u2 * (-1.0f / 6.0f + u2 * (1.0f / 120.0f - u2 * (1.0f / 5040.0f))));
+    if (kTier == kTierMixed && !(fabsf(u) < 0.5f)) amp0 = __builtin_amdgcn_sinf(hh - rintf(hh)) * q.inv_piphr;
+  } else {
+    amp0 = __builtin_amdgcn_sinf(hh - rintf(hh)) * q.inv_piphr;
+  }
   const float e3 = q.up3 ? fmaf(q.t3, cv.by, cv.bx) : fmaf(q.t3, cv.ay, cv.ax);
   float e2;
   if (kLinear) {
@@ -433,6 +451,43 @@ __device__ inline float2 term32(const Term32& q, int m, const StepLds* __restric
   }
   const float amp = __builtin_amdgcn_exp2f(e2) * amp0;
   return make_float2(amp * cs, amp * sn);
+}
+
+// Tier of one node from the plan's step extremes (LDS: steps grow with m).
+__device__ inline void node_tier_flags(const Term32& q, const StepLds* st, int M, bool* small, bool* large) {
+  const float ap = fabsf(q.phrf), tp = 2.0f * (float)kPi;
+  *small = ap * st[M - 1].zmf < 0.25f && tp * ap * st[M - 1].hdz < 0.5f;
+  *large = tp * ap * st[0].hdz >= 0.5f;
+}
+
+// Wave-uniform tier: every active lane must qualify.
+__device__ inline int wave_tier(bool small, bool large) {
+  if (__all(small)) return kTierSmall;
+  if (__all(large)) return kTierLarge;
+  return kTierMixed;
+}
+
+template <bool kLinear>
+__device__ inline float2 term32_tier(int tier, const Term32& q, int m, const StepLds* __restrict__ st,
+                                     const Col4* __restrict__ col, const float2* __restrict__ tab, int n) {
+  if (tier == kTierSmall) return term32<kLinear, kTierSmall>(q, m, st, col, tab, n);
+  if (tier == kTierLarge) return term32<kLinear, kTierLarge>(q, m, st, col, tab, n);
+  return term32<kLinear, kTierMixed>(q, m, st, col, tab, n);
+}
+
+// S = sum of the step terms of one node at a fixed tier.
+template <bool kLinear, int kTier, int kUnroll>
+__device__ inline void accumulate32(const Term32& q, const StepLds* __restrict__ st, const Col4* __restrict__ col,
+                                    const float2* __restrict__ tab, int n, int M, float* sr, float* si) {
+  float a = 0.0f, b = 0.0f;
+#pragma unroll kUnroll
+  for (int m = 0; m < M; ++m) {
+    const float2 t = term32<kLinear, kTier>(q, m, st, col, tab, n);
+    a += t.x;
+    b += t.y;
+  }
+  *sr = a;
+  *si = b;
 }
 
 // FP64 form of the same term (ocml sincospi / sinpi / exp on the FP64 table).

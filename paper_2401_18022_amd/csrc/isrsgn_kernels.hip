@@ -233,13 +233,13 @@ k_tiles(TileArgs A) {
         if (kPrec == 0) {
           const Term32 tq = term32_setup(nd, k, n);
           const float2* tab = A.w.lt32 + (size_t)M * o;
-          float sr = 0.0f, si = 0.0f;
-#pragma unroll kUnroll
-          for (int m = 0; m < M; ++m) {
-            const float2 a = term32<kLinear>(tq, m, steps, col, tab, n);
-            sr += a.x;
-            si += a.y;
-          }
+          bool small, large;
+          node_tier_flags(tq, steps, M, &small, &large);
+          const int tier = wave_tier(small, large);
+          float sr, si;
+          if (tier == kTierSmall) accumulate32<kLinear, kTierSmall, kUnroll>(tq, steps, col, tab, n, M, &sr, &si);
+          else if (tier == kTierLarge) accumulate32<kLinear, kTierLarge, kUnroll>(tq, steps, col, tab, n, M, &sr, &si);
+          else accumulate32<kLinear, kTierMixed, kUnroll>(tq, steps, col, tab, n, M, &sr, &si);
           s2v = (double)sr * sr + (double)si * si;
         } else {
           const Term64 tq = term64_setup(nd, i);

@@ -91,7 +91,7 @@ def segment_lbfgsb(engine, plan, x0_dbm=None, lo=-5.0, hi=5.0, pgtol=0.01, maxit
 
     x0 = np.zeros(A.shape[1]) if x0_dbm is None else np.asarray(x0_dbm, dtype=np.float64)
     res = minimize(fg, x0, jac=True, method="L-BFGS-B", bounds=[(lo, hi)] * A.shape[1],
-                   options=dict(pgtol=pgtol, maxiter=maxiter))
+                   options=dict(gtol=pgtol, maxiter=maxiter))
     return res.x, A @ res.x, hist, res, counts
 
 
