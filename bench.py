@@ -84,6 +84,10 @@ def main():
             return e.snr_grad(wl.plan, P, nf)
         return e.snr(wl.plan, P, nf)
 
+    def note(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    note(f"{'SNR+gradient' if grad else 'SNR'} step, FP32 form: warmup")
     for _ in range(args.warmup):
         step(eng)
     torch.cuda.synchronize()
@@ -94,6 +98,7 @@ def main():
         st = eng.stage_times()          # waits for this step's last event
         for k in stages:
             stages[k] += st[k]
+        note(f"timed step done in {st['total']:.0f} ms")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     thr = out[1].item()
@@ -109,8 +114,10 @@ def main():
 
     fp64 = None
     if not args.no_fp64:
+        note("FP64 form: first call (autotune)")
         e64 = make(W.FP64)
         step(e64)
+        note("FP64 form: timed call")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         step(e64)
@@ -122,6 +129,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
+        note("CPU oracle sample")
         from oracle import oracle as orc
         sample_coi = [n // 2]
         o = orc.Oracle(wl.fibre, wl.plan)

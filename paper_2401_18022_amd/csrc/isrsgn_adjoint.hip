@@ -53,15 +53,16 @@ __global__ void k_zero_counter2(unsigned int* c) { *c = 0u; }
 // Scatter: after a node batch has S (pass 1), the batch recomputes its terms in chunks of MC
 // steps (pass 2) and stages Q in LDS; then the lanes are re-mapped to (step, node group):
 // each lane walks its group's nodes in row order, keeping running sums while the f1 (f2)
-// segment stays the same and flushing them with one FP64 atomic per (segment, step) when it
-// changes -- along a row f1 and f2 move monotonically, so runs are long.  The f3 and f_i
-// contributions only touch channels k-1, k, k+1 and i: they accumulate in LDS per tile.
-struct AdjMeta {
-  int s1, s2;
-  float t1, t2, w3a, w3b, w3c, wi;  // wi: weight of the f_i term (0 for the linear profile)
-  int valid;
-  int pad;
-};
+// segment stays the same and flushing them when it changes -- along a row f1 and f2 move
+// monotonically, so runs are long.  Flushes to the tile's hot channels (k-1, k, k+1, i-1, i,
+// i+1) land in per-tile LDS rows; the rest go to HBM with FP64 atomics.  The f3 and f_i
+// contributions only touch channels k-1, k, k+1 and i: they accumulate in the LDS rows too.
+// Staging and metadata are private to a wave, so the re-map needs wave-level ordering only.
+//
+// Per-node metadata, struct of arrays, group g of MC nodes starting at g (MC + 1) so that the
+// groups a wave reads at once sit in distinct LDS banks:
+//   key: s1 | s2 << 16 (-1: node off the support), t1, t2, w3a, w3c; w3b = wgt - w3a - w3c.
+constexpr int kMetaStride = 72;  // >= 64 + 64 / MC for MC in {8, 16}
 
 template <int kPrec>
 struct AdjCfg {
@@ -77,8 +78,26 @@ struct AdjCfg<1> {
 __host__ __device__ inline size_t adjoint_lds_bytes(int nmax, int gs, int M, int prec) {
   const int mc = prec == 0 ? 16 : 8;
   const size_t rb = prec == 0 ? 4 : 8;
-  return sizeof(double) * (4 * (size_t)nmax + 4 * (size_t)gs + (size_t)nmax + 4 * (size_t)M + 8) +
-         (sizeof(StepLds) + sizeof(Col4)) * (size_t)M + 4 * (size_t)mc * 65 * rb + 4 * 64 * sizeof(AdjMeta) + 16;
+  return sizeof(double) * (4 * (size_t)nmax + 4 * (size_t)gs + (size_t)nmax + 6 * (size_t)M + 8) +
+         (sizeof(StepLds) + sizeof(Col4)) * (size_t)M + 4 * (size_t)mc * 65 * rb + 4 * 5 * kMetaStride * 4 + 16;
+}
+
+// Pass 2 of the FP32 form for one chunk of MC steps at a fixed accuracy tier:
+// out[mm * 65] = cq Re(conj(S) term_{m0+mm}).
+template <bool kLinear, int kTier, int MC>
+__device__ inline void stage_chunk32(const Term32& t, bool valid, int m0, int M, float cq, float sr, float si,
+                                     const StepLds* __restrict__ st, const Col4* __restrict__ col,
+                                     const float2* __restrict__ tab, int n, float* out) {
+#pragma unroll 2
+  for (int mm = 0; mm < MC; ++mm) {
+    const int m = m0 + mm;
+    float qv = 0.0f;
+    if (valid && m < M) {
+      const float2 a = term32<kLinear, kTier>(t, m, st, col, tab, n);
+      qv = cq * fmaf(sr, a.x, si * a.y);
+    }
+    out[mm * 65] = qv;
+  }
 }
 
 struct AdjArgs {
@@ -104,15 +123,19 @@ __global__ void __launch_bounds__(kTileBlock) k_adjoint(AdjArgs A) {
   d += 4 * GS;
   double* gGl = d;
   d += nmax;
-  double* tacc = d;  // [4][M]: channels k-1, k, k+1, i
-  d += 4 * M;
+  double* tacc = d;  // [6][M]: the tile's hot channels k-1, k, k+1, i-1, i, i+1
+  d += 6 * M;
   double* red = d;
   d += 8;
   StepLds* steps = reinterpret_cast<StepLds*>(d);
   Col4* col = reinterpret_cast<Col4*>(steps + M);
   real* stage = reinterpret_cast<real*>(col + M);  // [4 waves][MC][65] (odd row stride: no bank conflicts)
-  AdjMeta* meta = reinterpret_cast<AdjMeta*>(stage + 4 * MC * 65);  // [4 waves][64]
-  unsigned int* tile_slot = reinterpret_cast<unsigned int*>(meta + 4 * 64);
+  int* mkey = reinterpret_cast<int*>(stage + 4 * MC * 65) + wv * kMetaStride;  // this wave's metadata
+  float* mt1 = reinterpret_cast<float*>(mkey) + 4 * kMetaStride;
+  float* mt2 = mt1 + 4 * kMetaStride;
+  float* mw3a = mt2 + 4 * kMetaStride;
+  float* mw3c = mw3a + 4 * kMetaStride;
+  unsigned int* tile_slot = reinterpret_cast<unsigned int*>(reinterpret_cast<int*>(stage + 4 * MC * 65) + 20 * kMetaStride);
   const PlanView& pv = A.pv;
   unsigned int* counter = A.w.counter + 2;
   int cur_b = -1;
@@ -136,13 +159,16 @@ __global__ void __launch_bounds__(kTileBlock) k_adjoint(AdjArgs A) {
     }
     if (kPrec == 0) load_cols<kLinear>(col, A.w.lt32 + (size_t)M * o, n, M, i, k);
     for (int c = tid; c < n; c += kTileBlock) gGl[c] = 0.0;
-    for (int q = tid; q < 4 * M; q += kTileBlock) tacc[q] = 0.0;
+    for (int q = tid; q < 6 * M; q += kTileBlock) tacc[q] = 0.0;
     __syncthreads();
-    const TileGeo g = tile_geo(ch, n, i, k, A.fp.f_ref);
+    const TileGeo g = uniform_geo(tile_geo(ch, n, i, k, A.fp.f_ref));
     const double* zm = A.w.zm + (size_t)b * M;
     const double* dz = A.w.dz + (size_t)b * M;
     const float* hdz = A.w.hdz32 + (size_t)b * M;
     double* gL = A.w.gL + (size_t)M * o;  // [c][m]
+    // Most f1/f2 runs sit next to the interferer or the COI (rows near the axes): their sums go
+    // to per-tile LDS rows and reach HBM once per tile; other channels go straight to HBM.
+    const int hot[6] = {k - 1, k, k + 1, i - 1, i, i + 1};
     double gk_acc = 0.0;
     for (int part = kQ1; part <= kQ4; ++part) {
       if (!layout_rows(rw, g, part, GS, GV, A.fp.s_decades)) continue;
@@ -166,9 +192,9 @@ __global__ void __launch_bounds__(kTileBlock) k_adjoint(AdjArgs A) {
           if (kPrec == 0) {
             const float2* tab = A.w.lt32 + (size_t)M * o;
             float a32, b32;
-            if (tier == kTierSmall) accumulate32<kLinear, kTierSmall, 4>(t32, steps, col, tab, n, M, &a32, &b32);
-            else if (tier == kTierLarge) accumulate32<kLinear, kTierLarge, 4>(t32, steps, col, tab, n, M, &a32, &b32);
-            else accumulate32<kLinear, kTierMixed, 4>(t32, steps, col, tab, n, M, &a32, &b32);
+            if (tier == kTierSmall) accumulate32<kLinear, kTierSmall, 2>(t32, steps, col, tab, n, M, &a32, &b32);
+            else if (tier == kTierLarge) accumulate32<kLinear, kTierLarge, 2>(t32, steps, col, tab, n, M, &a32, &b32);
+            else accumulate32<kLinear, kTierMixed, 2>(t32, steps, col, tab, n, M, &a32, &b32);
             sr = a32;
             si = b32;
           } else {
@@ -187,93 +213,113 @@ __global__ void __launch_bounds__(kTileBlock) k_adjoint(AdjArgs A) {
           gk_acc += base2 * ch.psd[nd.c1] * ch.psd[nd.c2];
         }
         const real cq = valid ? (real)(lam * nd.w * nd.gprod) : (real)0;
-        AdjMeta mt{};
-        mt.valid = valid ? 1 : 0;
-        if (valid) {
-          const float t3 = (float)nd.t3;
-          const float wgt = kLinear ? 2.0f : 1.0f;
-          const bool lower = nd.s3 < k;  // segment (k-1, k) or (k, k+1)
-          mt.w3a = lower ? wgt * (1.0f - t3) : 0.0f;
-          mt.w3b = lower ? wgt * t3 : wgt * (1.0f - t3);
-          mt.w3c = lower ? 0.0f : wgt * t3;
-          if (n == 1) { mt.w3a = 0.0f; mt.w3b = wgt; mt.w3c = 0.0f; }
-          mt.s1 = kLinear ? -1 : nd.s1;
-          mt.s2 = kLinear ? -1 : nd.s2;
-          mt.t1 = (float)nd.t1;
-          mt.t2 = (float)nd.t2;
-          mt.wi = kLinear ? 0.0f : 1.0f;
+        const float wgt = kLinear ? 2.0f : 1.0f;
+        {
+          const int jm = lane + lane / MC;
+          int key = -1;
+          float w3a = 0.0f, w3c = 0.0f;
+          if (valid) {
+            const float t3 = (float)nd.t3;
+            if (n > 1) {
+              const bool lower = nd.s3 < k;  // segment (k-1, k) or (k, k+1)
+              w3a = lower ? wgt * (1.0f - t3) : 0.0f;
+              w3c = lower ? 0.0f : wgt * t3;
+            }
+            key = kLinear ? -1 : (nd.s1 | (nd.s2 << 16));
+          }
+          mkey[jm] = key;
+          mt1[jm] = valid ? (float)nd.t1 : 0.0f;
+          mt2[jm] = valid ? (float)nd.t2 : 0.0f;
+          mw3a[jm] = w3a;
+          mw3c[jm] = w3c;
         }
-        meta[wv * 64 + lane] = mt;
+        real* my_stage = stage + (size_t)wv * MC * 65;
         // pass 2 in chunks of MC steps
         for (int m0 = 0; m0 < M; m0 += MC) {
-#pragma unroll
-          for (int mm = 0; mm < MC; ++mm) {
-            const int m = m0 + mm;
-            real qv = 0;
-            if (valid && m < M) {
-              if (kPrec == 0) {
-                const float2 a = term32_tier<kLinear>(tier, t32, m, steps, col, A.w.lt32 + (size_t)M * o, n);
-                qv = (real)(cq * (sr * a.x + si * a.y));
-              } else {
+          if (kPrec == 0) {
+            const float2* tab = A.w.lt32 + (size_t)M * o;
+            float* out = reinterpret_cast<float*>(my_stage) + lane;
+            if (tier == kTierSmall)
+              stage_chunk32<kLinear, kTierSmall, MC>(t32, valid, m0, M, (float)cq, (float)sr, (float)si, steps, col, tab, n, out);
+            else if (tier == kTierLarge)
+              stage_chunk32<kLinear, kTierLarge, MC>(t32, valid, m0, M, (float)cq, (float)sr, (float)si, steps, col, tab, n, out);
+            else
+              stage_chunk32<kLinear, kTierMixed, MC>(t32, valid, m0, M, (float)cq, (float)sr, (float)si, steps, col, tab, n, out);
+          } else {
+            for (int mm = 0; mm < MC; ++mm) {
+              const int m = m0 + mm;
+              real qv = 0;
+              if (valid && m < M) {
                 const double2 a = term64<kLinear>(t64, m, zm, dz, A.w.ell64 + (size_t)M * o, n);
                 qv = (real)(cq * (sr * a.x + si * a.y));
               }
+              my_stage[mm * 65 + lane] = qv;
             }
-            stage[(wv * MC + mm) * 65 + lane] = qv;
           }
-          __syncthreads();
+          __syncwarp();
           // re-mapped phase: lane -> (step m0 + mm, node group gr)
           {
             const int mm = lane % MC, gr = lane / MC, m = m0 + mm;
             const bool live = m < M;
+            const int jb = gr * (MC + 1);
+            const real* qrow = my_stage + mm * 65 + gr * MC;
             int cur1 = -1, cur2 = -1;
-            double a1lo = 0, a1hi = 0, a2lo = 0, a2hi = 0, x3a = 0, x3b = 0, x3c = 0, xi = 0;
+            // run sums in the form's precision (at most MC nodes each), flushed to FP64:
+            // a = sum q, ah = sum q t; the segment's lower channel gets a - ah, the upper ah
+            real a1 = 0, a1h = 0, a2 = 0, a2h = 0, qs = 0, x3a = 0, x3c = 0;
+            auto put = [=](int c, double v) {
+              int hs = -1;
+#pragma unroll
+              for (int q = 5; q >= 0; --q)
+                if (hot[q] == c) hs = q;
+              // distinct scopes keep the LDS and global adds apart (no flat atomic)
+              if (hs >= 0) __hip_atomic_fetch_add(&tacc[hs * M + m], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+              else __hip_atomic_fetch_add(&gL[(size_t)c * M + m], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            };
+            auto flush = [=](int cur, real a, real ah) {
+              if (!live || cur < 0) return;
+              put(cur, (double)(a - ah));
+              if (n > 1) put(cur + 1, (double)ah);
+            };
+#pragma unroll 4
             for (int it = 0; it < MC; ++it) {
-              const int j = gr * MC + it;
-              const AdjMeta mj = meta[wv * 64 + j];
-              if (!mj.valid) continue;
-              const double qv = (double)stage[(wv * MC + mm) * 65 + j];
-              if (mj.s1 != cur1) {
-                if (live && cur1 >= 0) {
-                  atomicAdd(&gL[(size_t)cur1 * M + m], a1lo);
-                  if (n > 1) atomicAdd(&gL[(size_t)(cur1 + 1) * M + m], a1hi);
+              const real qv = qrow[it];
+              qs += qv;
+              x3a += qv * (real)mw3a[jb + it];
+              x3c += qv * (real)mw3c[jb + it];
+              if (!kLinear) {
+                const int key = mkey[jb + it];
+                if (key >= 0) {
+                  const int s1 = key & 0xffff, s2 = key >> 16;
+                  if (s1 != cur1) {
+                    flush(cur1, a1, a1h);
+                    cur1 = s1;
+                    a1 = a1h = (real)0;
+                  }
+                  if (s2 != cur2) {
+                    flush(cur2, a2, a2h);
+                    cur2 = s2;
+                    a2 = a2h = (real)0;
+                  }
+                  a1 += qv;
+                  a1h += qv * (real)mt1[jb + it];
+                  a2 += qv;
+                  a2h += qv * (real)mt2[jb + it];
                 }
-                cur1 = mj.s1;
-                a1lo = a1hi = 0.0;
               }
-              if (mj.s2 != cur2) {
-                if (live && cur2 >= 0) {
-                  atomicAdd(&gL[(size_t)cur2 * M + m], a2lo);
-                  if (n > 1) atomicAdd(&gL[(size_t)(cur2 + 1) * M + m], a2hi);
-                }
-                cur2 = mj.s2;
-                a2lo = a2hi = 0.0;
-              }
-              a1lo += qv * (1.0 - mj.t1);
-              a1hi += qv * mj.t1;
-              a2lo += qv * (1.0 - mj.t2);
-              a2hi += qv * mj.t2;
-              x3a += qv * mj.w3a;
-              x3b += qv * mj.w3b;
-              x3c += qv * mj.w3c;
-              xi += qv * mj.wi;
+            }
+            if (!kLinear) {
+              flush(cur1, a1, a1h);
+              flush(cur2, a2, a2h);
             }
             if (live) {
-              if (cur1 >= 0) {
-                atomicAdd(&gL[(size_t)cur1 * M + m], a1lo);
-                if (n > 1) atomicAdd(&gL[(size_t)(cur1 + 1) * M + m], a1hi);
-              }
-              if (cur2 >= 0) {
-                atomicAdd(&gL[(size_t)cur2 * M + m], a2lo);
-                if (n > 1) atomicAdd(&gL[(size_t)(cur2 + 1) * M + m], a2hi);
-              }
-              atomicAdd(&tacc[0 * M + m], x3a);
-              atomicAdd(&tacc[1 * M + m], x3b);
-              atomicAdd(&tacc[2 * M + m], x3c);
-              atomicAdd(&tacc[3 * M + m], xi);
+              atomicAdd(&tacc[0 * M + m], (double)x3a);
+              atomicAdd(&tacc[1 * M + m], (double)((real)wgt * qs - x3a - x3c));
+              atomicAdd(&tacc[2 * M + m], (double)x3c);
+              if (!kLinear) atomicAdd(&tacc[4 * M + m], -(double)qs);
             }
           }
-          __syncthreads();
+          __syncwarp();  // the next chunk overwrites this wave's staging
         }
       }
       __syncthreads();
@@ -284,10 +330,9 @@ __global__ void __launch_bounds__(kTileBlock) k_adjoint(AdjArgs A) {
     __syncthreads();
     for (int c = tid; c < n; c += kTileBlock)
       if (gGl[c] != 0.0) atomicAdd(&A.w.gG[o + c], gGl[c]);
-    for (int q = tid; q < 4 * M; q += kTileBlock) {
-      const int which = q / M, m = q % M;
-      const int c = which == 0 ? k - 1 : (which == 1 ? k : (which == 2 ? k + 1 : i));
-      const double v = which == 3 ? -tacc[q] : tacc[q];
+    for (int q = tid; q < 6 * M; q += kTileBlock) {
+      const int c = hot[q / M], m = q % M;
+      const double v = tacc[q];
       if (v != 0.0 && c >= 0 && c < n) atomicAdd(&gL[(size_t)c * M + m], v);
     }
     __syncthreads();

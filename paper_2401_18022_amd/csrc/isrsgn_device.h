@@ -275,6 +275,26 @@ __device__ inline TileGeo tile_geo(const ChanLds& ch, int n, int i, int k, doubl
   return g;
 }
 
+// The tile geometry is the same for every lane but comes from LDS loads, which the compiler
+// keeps in vector registers; moving it to scalar registers frees 14 VGPRs per lane.
+__device__ inline double uniform_f64(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffLL));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ inline TileGeo uniform_geo(TileGeo g) {
+  g.fi = uniform_f64(g.fi);
+  g.xp = uniform_f64(g.xp);
+  g.xn = uniform_f64(g.xn);
+  g.slo = uniform_f64(g.slo);
+  g.shi = uniform_f64(g.shi);
+  g.wi = uniform_f64(g.wi);
+  g.gk = uniform_f64(g.gk);
+  return g;
+}
+
 // Lays out the rows of one part in LDS (all threads of the block); false if the part is empty.
 __device__ inline bool layout_rows(const RowLds& rw, const TileGeo& g, int part, int gs, int gv, double s_decades) {
   double umax;

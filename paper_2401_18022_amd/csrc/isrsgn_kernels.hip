@@ -219,7 +219,7 @@ k_tiles(TileArgs A) {
     }
     if (kPrec == 0) load_cols<kLinear>(col, A.w.lt32 + (size_t)M * o, n, M, i, k);
     __syncthreads();
-    const TileGeo g = tile_geo(ch, n, i, k, A.fp.f_ref);
+    const TileGeo g = uniform_geo(tile_geo(ch, n, i, k, A.fp.f_ref));
     double acc = 0.0;
     unsigned int evaluated = 0;
     for (int part = kQ1; part <= kQ4; ++part) {
