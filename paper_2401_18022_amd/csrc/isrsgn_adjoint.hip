@@ -88,15 +88,27 @@ template <bool kLinear, int kTier, int MC>
 __device__ inline void stage_chunk32(const Term32& t, bool valid, int m0, int M, float cq, float sr, float si,
                                      const StepLds* __restrict__ st, const Col4* __restrict__ col,
                                      const float2* __restrict__ tab, int n, float* out) {
+  if (!valid) {  // one branch per chunk, not per step
+#pragma unroll
+    for (int mm = 0; mm < MC; ++mm) out[mm * 65] = 0.0f;
+    return;
+  }
+  if (m0 + MC <= M) {
 #pragma unroll 2
-  for (int mm = 0; mm < MC; ++mm) {
-    const int m = m0 + mm;
-    float qv = 0.0f;
-    if (valid && m < M) {
-      const float2 a = term32<kLinear, kTier>(t, m, st, col, tab, n);
-      qv = cq * fmaf(sr, a.x, si * a.y);
+    for (int mm = 0; mm < MC; ++mm) {
+      const float2 a = term32<kLinear, kTier>(t, m0 + mm, st, col, tab, n);
+      out[mm * 65] = cq * fmaf(sr, a.x, si * a.y);
     }
-    out[mm * 65] = qv;
+  } else {
+    for (int mm = 0; mm < MC; ++mm) {
+      const int m = m0 + mm;
+      float qv = 0.0f;
+      if (m < M) {
+        const float2 a = term32<kLinear, kTier>(t, m, st, col, tab, n);
+        qv = cq * fmaf(sr, a.x, si * a.y);
+      }
+      out[mm * 65] = qv;
+    }
   }
 }
 
@@ -131,10 +143,9 @@ __global__ void __launch_bounds__(kTileBlock) k_adjoint(AdjArgs A) {
   Col4* col = reinterpret_cast<Col4*>(steps + M);
   real* stage = reinterpret_cast<real*>(col + M);  // [4 waves][MC][65] (odd row stride: no bank conflicts)
   int* mkey = reinterpret_cast<int*>(stage + 4 * MC * 65) + wv * kMetaStride;  // this wave's metadata
-  float* mt1 = reinterpret_cast<float*>(mkey) + 4 * kMetaStride;
-  float* mt2 = mt1 + 4 * kMetaStride;
-  float* mw3a = mt2 + 4 * kMetaStride;
-  float* mw3c = mw3a + 4 * kMetaStride;
+  float2* mt12 = reinterpret_cast<float2*>(reinterpret_cast<int*>(stage + 4 * MC * 65) + 4 * kMetaStride) +
+                 wv * kMetaStride;                                              // (t1, t2)
+  float2* mw3 = mt12 + 4 * kMetaStride;                                          // (w3a, w3c)
   unsigned int* tile_slot = reinterpret_cast<unsigned int*>(reinterpret_cast<int*>(stage + 4 * MC * 65) + 20 * kMetaStride);
   const PlanView& pv = A.pv;
   unsigned int* counter = A.w.counter + 2;
@@ -178,6 +189,41 @@ __global__ void __launch_bounds__(kTileBlock) k_adjoint(AdjArgs A) {
         const int64_t q = base + tid;
         Node nd;
         const bool valid = q < nodes && make_node(ch, rw, g, n, k, part, (int)(q / GV), (int)(q % GV), A.fp, &nd);
+        // per-node values used after pass 1 (taken now: the node's other fields die here)
+        const real cq = valid ? (real)(lam * nd.w * nd.gprod) : (real)0;
+        const double lw = valid ? lam * nd.w : 0.0;
+        const int c1 = valid ? nd.c1 : 0, c2 = valid ? nd.c2 : 0;
+        const float wgt = kLinear ? 2.0f : 1.0f;
+        int gkey;
+        bool one_run;
+        {
+          const int jm = lane + lane / MC;
+          int key = -1;
+          float w3a = 0.0f, w3c = 0.0f;
+          if (valid) {
+            const float t3 = (float)nd.t3;
+            if (n > 1) {
+              const bool lower = nd.s3 < k;  // segment (k-1, k) or (k, k+1)
+              w3a = lower ? wgt * (1.0f - t3) : 0.0f;
+              w3c = lower ? 0.0f : wgt * t3;
+            }
+            key = kLinear ? -1 : (nd.s1 | (nd.s2 << 16));
+          }
+          mkey[jm] = key;
+          mt12[jm] = valid ? make_float2((float)nd.t1, (float)nd.t2) : make_float2(0.0f, 0.0f);
+          mw3[jm] = make_float2(w3a, w3c);
+          // most groups of MC nodes lie in one f1 segment and one f2 segment (one run each);
+          // a wave whose groups all do takes the branch-free re-map below
+          int kmin = key >= 0 ? key : 0x7fffffff, kmax = key;
+#pragma unroll
+          for (int sh = 1; sh < MC; sh <<= 1) {
+            kmin = min(kmin, __shfl_xor(kmin, sh));
+            kmax = max(kmax, __shfl_xor(kmax, sh));
+          }
+          gkey = kmax;  // the group's key when it has one run (-1: no node on the support)
+          one_run = kmax < 0 || kmin == kmax;
+        }
+        const bool wave_one_run = __all(one_run);
         // pass 1: S
         real sr = 0, si = 0;
         Term32 t32;
@@ -207,31 +253,10 @@ __global__ void __launch_bounds__(kTileBlock) k_adjoint(AdjArgs A) {
             }
           }
           const double s2 = (double)sr * sr + (double)si * si;
-          const double base2 = lam * nd.w * s2;
-          atomicAdd(&gGl[nd.c1], base2 * ch.psd[nd.c2] * g.gk);
-          atomicAdd(&gGl[nd.c2], base2 * ch.psd[nd.c1] * g.gk);
-          gk_acc += base2 * ch.psd[nd.c1] * ch.psd[nd.c2];
-        }
-        const real cq = valid ? (real)(lam * nd.w * nd.gprod) : (real)0;
-        const float wgt = kLinear ? 2.0f : 1.0f;
-        {
-          const int jm = lane + lane / MC;
-          int key = -1;
-          float w3a = 0.0f, w3c = 0.0f;
-          if (valid) {
-            const float t3 = (float)nd.t3;
-            if (n > 1) {
-              const bool lower = nd.s3 < k;  // segment (k-1, k) or (k, k+1)
-              w3a = lower ? wgt * (1.0f - t3) : 0.0f;
-              w3c = lower ? 0.0f : wgt * t3;
-            }
-            key = kLinear ? -1 : (nd.s1 | (nd.s2 << 16));
-          }
-          mkey[jm] = key;
-          mt1[jm] = valid ? (float)nd.t1 : 0.0f;
-          mt2[jm] = valid ? (float)nd.t2 : 0.0f;
-          mw3a[jm] = w3a;
-          mw3c[jm] = w3c;
+          const double base2 = lw * s2, p1 = ch.psd[c1], p2 = ch.psd[c2];
+          atomicAdd(&gGl[c1], base2 * p2 * g.gk);
+          atomicAdd(&gGl[c2], base2 * p1 * g.gk);
+          gk_acc += base2 * p1 * p2;
         }
         real* my_stage = stage + (size_t)wv * MC * 65;
         // pass 2 in chunks of MC steps
@@ -281,36 +306,58 @@ __global__ void __launch_bounds__(kTileBlock) k_adjoint(AdjArgs A) {
               put(cur, (double)(a - ah));
               if (n > 1) put(cur + 1, (double)ah);
             };
+            if (wave_one_run) {
 #pragma unroll 4
-            for (int it = 0; it < MC; ++it) {
-              const real qv = qrow[it];
-              qs += qv;
-              x3a += qv * (real)mw3a[jb + it];
-              x3c += qv * (real)mw3c[jb + it];
-              if (!kLinear) {
-                const int key = mkey[jb + it];
-                if (key >= 0) {
-                  const int s1 = key & 0xffff, s2 = key >> 16;
-                  if (s1 != cur1) {
-                    flush(cur1, a1, a1h);
-                    cur1 = s1;
-                    a1 = a1h = (real)0;
-                  }
-                  if (s2 != cur2) {
-                    flush(cur2, a2, a2h);
-                    cur2 = s2;
-                    a2 = a2h = (real)0;
-                  }
-                  a1 += qv;
-                  a1h += qv * (real)mt1[jb + it];
-                  a2 += qv;
-                  a2h += qv * (real)mt2[jb + it];
+              for (int it = 0; it < MC; ++it) {
+                const real qv = qrow[it];
+                const float2 w3 = mw3[jb + it];
+                qs += qv;
+                x3a += qv * (real)w3.x;
+                x3c += qv * (real)w3.y;
+                if (!kLinear) {
+                  const float2 tt = mt12[jb + it];
+                  a1h += qv * (real)tt.x;
+                  a2h += qv * (real)tt.y;
                 }
               }
-            }
-            if (!kLinear) {
-              flush(cur1, a1, a1h);
-              flush(cur2, a2, a2h);
+              if (!kLinear && gkey >= 0) {
+                flush(gkey & 0xffff, qs, a1h);
+                flush(gkey >> 16, qs, a2h);
+              }
+            } else {
+#pragma unroll 4
+              for (int it = 0; it < MC; ++it) {
+                const real qv = qrow[it];
+                qs += qv;
+                const float2 w3 = mw3[jb + it];
+                x3a += qv * (real)w3.x;
+                x3c += qv * (real)w3.y;
+                if (!kLinear) {
+                  const int key = mkey[jb + it];
+                  if (key >= 0) {
+                    const int s1 = key & 0xffff, s2 = key >> 16;
+                    if (s1 != cur1) {
+                      flush(cur1, a1, a1h);
+                      cur1 = s1;
+                      a1 = a1h = (real)0;
+                    }
+                    if (s2 != cur2) {
+                      flush(cur2, a2, a2h);
+                      cur2 = s2;
+                      a2 = a2h = (real)0;
+                    }
+                    const float2 tt = mt12[jb + it];
+                    a1 += qv;
+                    a1h += qv * (real)tt.x;
+                    a2 += qv;
+                    a2h += qv * (real)tt.y;
+                  }
+                }
+              }
+              if (!kLinear) {
+                flush(cur1, a1, a1h);
+                flush(cur2, a2, a2h);
+              }
             }
             if (live) {
               atomicAdd(&tacc[0 * M + m], (double)x3a);
