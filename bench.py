@@ -1,6 +1,7 @@
 """Benchmark of the ISRS GN pair-integral engine on one MI355X.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-fp64] [--grad|--no-grad]
+                    [--copy-probe MIB]
 
 One step = one full pass of the hot path on the O-to-U system (589 x 96 GBaud,
 1260-1675 nm, 80 km SSMF, G=128, N_M=112, FP32 form): distance steps, ODE power
@@ -12,8 +13,10 @@ in HBM before the timed region.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -29,6 +32,41 @@ SLOTS_PER_NODE_STEP = 30
 FLOP_EQ_PER_SLOT = 2            # one FMA slot = 2 FLOP at the FP32 vector peak
 PEAK_FP32_TFLOPS = 157.3        # MI355X FP32 vector (no matrix cores)
 
+# HBM traffic per launch of the dominant kernels comes from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# runs recorded in profiles/; it is reported only while the kernel's sources are unchanged.
+CSRC = os.path.join(ROOT, "paper_2401_18022_amd", "csrc")
+TRAFFIC_RECORDS = {
+    "pair_integral_forward": ("pair_integral_forward_ou589_g128_fp32.md",
+                              ["isrsgn_kernels.hip", "isrsgn_device.h", "isrsgn_internal.h"]),
+    "pair_integral_adjoint": ("pair_integral_adjoint_ou589_g128_fp32.md",
+                              ["isrsgn_adjoint.hip", "isrsgn_device.h", "isrsgn_internal.h"]),
+}
+
+
+def kernel_sources_sha256(files):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel, grid):
+    """(fetch, write) bytes per launch from the profile record, or None if absent or stale."""
+    if kernel not in TRAFFIC_RECORDS or grid != 128:
+        return None
+    name, files = TRAFFIC_RECORDS[kernel]
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    sha = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
+    fetch = re.search(r"fetch_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    write = re.search(r"write_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not (sha and fetch and write) or sha.group(1) != kernel_sources_sha256(files):
+        return None
+    return float(fetch.group(1)), float(write.group(1)), "profiles/" + name
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -40,6 +78,8 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip timing the FP64 GPU form")
     ap.add_argument("--grad", dest="grad", action="store_true", default=None)
     ap.add_argument("--no-grad", dest="grad", action="store_false")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device to device (calibrates rocprofv3 byte counters)")
     return ap.parse_args()
 
 
@@ -57,6 +97,11 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.copy_probe > 0:
+        src = torch.ones(args.copy_probe << 18, dtype=torch.float32, device="cuda")
+        torch.empty_like(src).copy_(src)
+        torch.cuda.synchronize()
+        del src
     wl = W.config_ou(grid_s=args.grid, grid_v=args.grid)
     n = len(wl.plan.f_hz)
     P = torch.tensor(wl.plan.p_w, dtype=torch.float64, device="cuda")
@@ -111,6 +156,7 @@ def main():
     if grad and stages["adjoint_tiles"] / args.steps > tiles_ms:
         dominant, dom_ms, dom_sweeps = "pair_integral_adjoint", stages["adjoint_tiles"] / args.steps, 2
     achieved = dom_sweeps * node_steps * SLOTS_PER_NODE_STEP * FLOP_EQ_PER_SLOT / (dom_ms * 1e-3) / 1e12
+    rec = recorded_traffic(dominant, args.grid)
 
     fp64 = None
     if not args.no_fp64:
@@ -159,7 +205,9 @@ def main():
                                + ("SNR + adjoint gradient" if grad else "SNR (forward) only"),
                    "pairs_per_step": n * n, "grad": bool(grad)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None, "kernel": dominant,
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": (rec[0] + rec[1]) if rec else None,
+                     "traffic_fetch_write_bytes": [rec[0], rec[1]] if rec else None,
+                     "traffic_source": rec[2] if rec else None, "kernel": dominant,
                      "kernel_ms": dom_ms, "node_steps_per_launch": dom_sweeps * node_steps,
                      "slots_per_node_step": SLOTS_PER_NODE_STEP, "tile_variant": work["variant"]},
         "cpu_baseline": cpu,
