@@ -87,7 +87,7 @@ __host__ __device__ inline size_t adjoint_lds_bytes(int nmax, int gs, int M, int
 template <bool kLinear, int kTier, int MC>
 __device__ inline void stage_chunk32(const Term32& t, bool valid, int m0, int M, float cq, float sr, float si,
                                      const StepLds* __restrict__ st, const Col4* __restrict__ col,
-                                     const float2* __restrict__ tab, int n, float* out) {
+                                     const Tab32& tab, int n, float* out) {
   if (!valid) {  // one branch per chunk, not per step
 #pragma unroll
     for (int mm = 0; mm < MC; ++mm) out[mm * 65] = 0.0f;
@@ -236,11 +236,11 @@ __global__ void __launch_bounds__(kTileBlock) k_adjoint(AdjArgs A) {
         const int tier = wave_tier(tsmall, tlarge);
         if (valid) {
           if (kPrec == 0) {
-            const float2* tab = A.w.lt32 + (size_t)M * o;
+            const Tab32 tab = make_tab32(A.w.lt32 + (size_t)M * o, n, M);
             float a32, b32;
-            if (tier == kTierSmall) accumulate32<kLinear, kTierSmall, 2>(t32, steps, col, tab, n, M, &a32, &b32);
-            else if (tier == kTierLarge) accumulate32<kLinear, kTierLarge, 2>(t32, steps, col, tab, n, M, &a32, &b32);
-            else accumulate32<kLinear, kTierMixed, 2>(t32, steps, col, tab, n, M, &a32, &b32);
+            if (tier == kTierSmall) accumulate32<kLinear, kTierSmall, 4>(t32, steps, col, tab, n, M, &a32, &b32);
+            else if (tier == kTierLarge) accumulate32<kLinear, kTierLarge, 4>(t32, steps, col, tab, n, M, &a32, &b32);
+            else accumulate32<kLinear, kTierMixed, 4>(t32, steps, col, tab, n, M, &a32, &b32);
             sr = a32;
             si = b32;
           } else {
@@ -262,7 +262,7 @@ __global__ void __launch_bounds__(kTileBlock) k_adjoint(AdjArgs A) {
         // pass 2 in chunks of MC steps
         for (int m0 = 0; m0 < M; m0 += MC) {
           if (kPrec == 0) {
-            const float2* tab = A.w.lt32 + (size_t)M * o;
+            const Tab32 tab = make_tab32(A.w.lt32 + (size_t)M * o, n, M);
             float* out = reinterpret_cast<float*>(my_stage) + lane;
             if (tier == kTierSmall)
               stage_chunk32<kLinear, kTierSmall, MC>(t32, valid, m0, M, (float)cq, (float)sr, (float)si, steps, col, tab, n, out);

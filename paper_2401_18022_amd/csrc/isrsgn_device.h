@@ -372,8 +372,8 @@ struct Col4 {
 struct Term32 {
   double phr;
   float phrf, inv_piphr, t1, t2, t3;
-  int s1, s2;
-  bool up3;  // f3 uses segment B
+  unsigned o1, o2;  // byte offsets of the f1 / f2 segments within a table row
+  bool up3;         // f3 uses segment B
 };
 
 __device__ inline Term32 term32_setup(const Node& nd, int k, int n) {
@@ -384,8 +384,8 @@ __device__ inline Term32 term32_setup(const Node& nd, int k, int n) {
   q.t1 = (float)nd.t1;
   q.t2 = (float)nd.t2;
   q.t3 = (float)nd.t3;
-  q.s1 = nd.s1;
-  q.s2 = nd.s2;
+  q.o1 = (unsigned)nd.s1 * (unsigned)sizeof(float2);
+  q.o2 = (unsigned)nd.s2 * (unsigned)sizeof(float2);
   const int segb = k < n - 2 ? k : (n - 2 > 0 ? n - 2 : 0);
   q.up3 = nd.s3 == segb;
   return q;
@@ -426,6 +426,25 @@ __device__ inline void load_steps(StepLds* st, const double* __restrict__ zm, co
   }
 }
 
+// The plan's FP32 profile table [m][c] (float2: scaled ln rho and the slope to the next
+// channel) behind a raw buffer descriptor: per step the row offset is a scalar and each
+// node's segment offsets are fixed vector offsets, so the loads need no per-step vector
+// address arithmetic.  3rd-dword 0x00020000: raw 32-bit data format on gfx9.
+struct Tab32 {
+  __amdgpu_buffer_rsrc_t r;
+};
+
+__device__ inline Tab32 make_tab32(const float2* tab, int n, int M) {
+  return Tab32{__builtin_amdgcn_make_buffer_rsrc(const_cast<float2*>(tab), (short)0,
+                                                 (int)((unsigned)n * (unsigned)M * (unsigned)sizeof(float2)),
+                                                 0x00020000)};
+}
+
+__device__ inline float2 tab32_at(const Tab32& t, unsigned voff, unsigned soff) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(t.r, voff, soff, 0);
+  return make_float2(__uint_as_float(v[0]), __uint_as_float(v[1]));
+}
+
 // Accuracy tiers of the FP32 step term, chosen per wave (all its lanes must qualify):
 //   kTierSmall: |phi| z_max < 1/4 revolution and |phi dz_m / 2| < 1/2 at every step: the phase
 //               is formed in FP32 (error < 5e-8 revolutions) and the sinc factor is its Taylor
@@ -436,9 +455,10 @@ enum { kTierMixed = 0, kTierSmall = 1, kTierLarge = 2 };
 
 template <bool kLinear, int kTier>
 __device__ inline float2 term32(const Term32& q, int m, const StepLds* __restrict__ st, const Col4* __restrict__ col,
-                                const float2* __restrict__ tab, int n) {
+                                const Tab32& tab, int n) {
   const StepLds sv = st[m];
-  const Col4 cv = col[m];
+  // the f3 term uses one of the two column segments (fixed per node): load only that pair
+  const float2 cab = reinterpret_cast<const float2*>(col + m)[q.up3 ? 1 : 0];
   float fr;
   if (kTier == kTierSmall) {
     const float tt = q.phrf * sv.zmf;
@@ -460,13 +480,13 @@ __device__ inline float2 term32(const Term32& q, int m, const StepLds* __restric
   } else {
     amp0 = __builtin_amdgcn_sinf(hh - rintf(hh)) * q.inv_piphr;
   }
-  const float e3 = q.up3 ? fmaf(q.t3, cv.by, cv.bx) : fmaf(q.t3, cv.ay, cv.ax);
+  const float e3 = fmaf(q.t3, cab.y, cab.x);
   float e2;
   if (kLinear) {
     e2 = e3;
   } else {
-    const float2* row = tab + (size_t)m * n;
-    const float2 l1 = row[q.s1], l2 = row[q.s2];
+    const unsigned row = (unsigned)m * (unsigned)n * (unsigned)sizeof(float2);
+    const float2 l1 = tab32_at(tab, q.o1, row), l2 = tab32_at(tab, q.o2, row);
     e2 = fmaf(q.t1, l1.y, l1.x) + fmaf(q.t2, l2.y, l2.x) + e3;
   }
   const float amp = __builtin_amdgcn_exp2f(e2) * amp0;
@@ -489,7 +509,7 @@ __device__ inline int wave_tier(bool small, bool large) {
 
 template <bool kLinear>
 __device__ inline float2 term32_tier(int tier, const Term32& q, int m, const StepLds* __restrict__ st,
-                                     const Col4* __restrict__ col, const float2* __restrict__ tab, int n) {
+                                     const Col4* __restrict__ col, const Tab32& tab, int n) {
   if (tier == kTierSmall) return term32<kLinear, kTierSmall>(q, m, st, col, tab, n);
   if (tier == kTierLarge) return term32<kLinear, kTierLarge>(q, m, st, col, tab, n);
   return term32<kLinear, kTierMixed>(q, m, st, col, tab, n);
@@ -498,7 +518,7 @@ __device__ inline float2 term32_tier(int tier, const Term32& q, int m, const Ste
 // S = sum of the step terms of one node at a fixed tier.
 template <bool kLinear, int kTier, int kUnroll>
 __device__ inline void accumulate32(const Term32& q, const StepLds* __restrict__ st, const Col4* __restrict__ col,
-                                    const float2* __restrict__ tab, int n, int M, float* sr, float* si) {
+                                    const Tab32& tab, int n, int M, float* sr, float* si) {
   float a = 0.0f, b = 0.0f;
 #pragma unroll kUnroll
   for (int m = 0; m < M; ++m) {

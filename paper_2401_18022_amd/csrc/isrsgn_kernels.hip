@@ -232,7 +232,7 @@ k_tiles(TileArgs A) {
         double s2v;
         if (kPrec == 0) {
           const Term32 tq = term32_setup(nd, k, n);
-          const float2* tab = A.w.lt32 + (size_t)M * o;
+          const Tab32 tab = make_tab32(A.w.lt32 + (size_t)M * o, n, M);
           bool small, large;
           node_tier_flags(tq, steps, M, &small, &large);
           const int tier = wave_tier(small, large);
