@@ -13,9 +13,9 @@ namespace {
 // dT/dN_i * 16/27 gamma_i^2 R_i; gP_i starts as the direct dT/dP_i; gLL_i = dT/d ln rho(L, f_i)
 // through the ASE term.
 __global__ void k_grad_prep(PlanView pv, const double* __restrict__ P, const double* __restrict__ nf, double snr_trx,
-                            Work w) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= pv.n_total) return;
+                            Work w, int g_begin, int g_end) {
+  const int g = g_begin + blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= g_end) return;
   const double p = P[g], R = pv.R[g], f = pv.f[g], gm = pv.gamma[g];
   double lamN = 0.0, direct = 0.0, pase = 0.0;
   if (p > 0.0) {
@@ -33,7 +33,6 @@ __global__ void k_grad_prep(PlanView pv, const double* __restrict__ P, const dou
   w.lam[g] = lamN * (16.0 / 27.0) * gm * gm * R;
   w.gP[g] = direct;
   w.gLL[g] = -lamN * pase;
-  w.gG[g] = 0.0;
 }
 
 __global__ void k_fill(double* x, int64_t n) {
@@ -93,6 +92,7 @@ __device__ inline void stage_chunk32(const Term32& t, bool valid, int m0, int M,
     for (int mm = 0; mm < MC; ++mm) out[mm * 65] = 0.0f;
     return;
   }
+  if (kTier == kTierLarge) cq *= t.inv_piphr;  // the large tier's terms leave out 1 / (pi phr)
   if (m0 + MC <= M) {
 #pragma unroll 2
     for (int mm = 0; mm < MC; ++mm) {
@@ -118,9 +118,12 @@ struct AdjArgs {
   const double* P;
   Work w;
   int nmax;
+  unsigned int t_begin, t_end;  // tiles [t_begin, t_end) of the concatenated tile list
 };
 
-template <int kPrec, bool kLinear>
+// kStored (FP32 form): S of every node comes from w.s_store, written by the forward tile
+// kernel for the same row batch, instead of a recomputing sweep over the steps.
+template <int kPrec, bool kLinear, bool kStored>
 __global__ void __launch_bounds__(kTileBlock) k_adjoint(AdjArgs A) {
   using real = typename AdjCfg<kPrec>::real;
   constexpr int MC = AdjCfg<kPrec>::MC;
@@ -151,10 +154,10 @@ __global__ void __launch_bounds__(kTileBlock) k_adjoint(AdjArgs A) {
   unsigned int* counter = A.w.counter + 2;
   int cur_b = -1;
   for (;;) {
-    if (tid == 0) *tile_slot = atomicAdd(counter, 1u);
+    if (tid == 0) *tile_slot = A.t_begin + atomicAdd(counter, 1u);
     __syncthreads();
     const unsigned int t = *tile_slot;
-    if ((int64_t)t >= pv.n_tiles) break;
+    if (t >= A.t_end) break;
     int b, i, k;
     decode_tile(pv, t, &b, &i, &k);
     const int o = pv.off[b], n = pv.off[b + 1] - o;
@@ -235,7 +238,11 @@ __global__ void __launch_bounds__(kTileBlock) k_adjoint(AdjArgs A) {
         }
         const int tier = wave_tier(tsmall, tlarge);
         if (valid) {
-          if (kPrec == 0) {
+          if (kStored) {
+            const float2 sv = A.w.s_store[((int64_t)(t - A.t_begin) * 3 + part) * nodes + q];
+            sr = sv.x;
+            si = sv.y;
+          } else if (kPrec == 0) {
             const Tab32 tab = make_tab32(A.w.lt32 + (size_t)M * o, n, M);
             float a32, b32;
             if (tier == kTierSmall) accumulate32<kLinear, kTierSmall, 4>(t32, steps, col, tab, n, M, &a32, &b32);
@@ -547,42 +554,63 @@ __global__ void k_grad_final(PlanView pv, Work w, double* dthr) {
 
 size_t adjoint_lds(int nmax, int gs, int M, int prec) { return adjoint_lds_bytes(nmax, gs, M, prec); }
 
-int adjoint_blocks_per_cu(const FibreParams& fp, int nmax) {
+int adjoint_blocks_per_cu(const FibreParams& fp, int nmax, bool stored) {
   int nb = 0;
   const size_t shm = adjoint_lds_bytes(nmax, fp.grid_s, fp.n_steps, fp.precision);
-  hipError_t e;
-  if (fp.precision == 0)
-    e = fp.profile == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adjoint<0, true>, kTileBlock, shm)
-                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adjoint<0, false>, kTileBlock, shm);
-  else
-    e = fp.profile == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adjoint<1, true>, kTileBlock, shm)
-                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adjoint<1, false>, kTileBlock, shm);
-  if (e != hipSuccess || nb < 1) nb = 1;
+  const void* k;
+  if (fp.precision == 0) {
+    if (stored) k = fp.profile == 0 ? reinterpret_cast<const void*>(k_adjoint<0, true, true>)
+                                    : reinterpret_cast<const void*>(k_adjoint<0, false, true>);
+    else k = fp.profile == 0 ? reinterpret_cast<const void*>(k_adjoint<0, true, false>)
+                             : reinterpret_cast<const void*>(k_adjoint<0, false, false>);
+  } else {
+    k = fp.profile == 0 ? reinterpret_cast<const void*>(k_adjoint<1, true, false>)
+                        : reinterpret_cast<const void*>(k_adjoint<1, false, false>);
+  }
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kTileBlock, shm) != hipSuccess || nb < 1) nb = 1;
   return nb;
 }
 
-hipError_t launch_grad(const PlanView& pv, const FibreParams& fp, const double* P, const double* nf, double snr_trx,
-                       const Work& w, int nmax, int grid, double* coef, double* dthr, hipStream_t s,
-                       hipEvent_t mid_event) {
-  const int M = fp.n_steps;
-  hipLaunchKernelGGL(k_grad_prep, dim3((pv.n_total + 255) / 256), dim3(256), 0, s, pv, P, nf, snr_trx, w);
-  const int64_t ngl = (int64_t)M * pv.n_total;
+hipError_t launch_grad_init(const PlanView& pv, const FibreParams& fp, const Work& w, hipStream_t s) {
+  const int64_t ngl = (int64_t)fp.n_steps * pv.n_total;
   hipLaunchKernelGGL(k_fill, dim3((unsigned)((ngl + 255) / 256 < 4096 ? (ngl + 255) / 256 : 4096)), dim3(256), 0, s,
                      w.gL, ngl);
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)((pv.n_total + 255) / 256)), dim3(256), 0, s, w.gG, (int64_t)pv.n_total);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_rows(const PlanView& pv, const double* P, const double* nf, double snr_trx, const Work& w,
+                            int g_begin, int g_end, hipStream_t s) {
+  if (g_end <= g_begin) return hipSuccess;
+  hipLaunchKernelGGL(k_grad_prep, dim3((unsigned)((g_end - g_begin + 255) / 256)), dim3(256), 0, s, pv, P, nf,
+                     snr_trx, w, g_begin, g_end);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_tiles(const PlanView& pv, const FibreParams& fp, const double* P, const Work& w, int nmax,
+                                int grid, unsigned int t_begin, unsigned int t_end, bool stored, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_counter2, dim3(1), dim3(1), 0, s, w.counter + 2);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  AdjArgs a{pv, fp, P, w, nmax};
-  const size_t shm = adjoint_lds_bytes(nmax, fp.grid_s, M, fp.precision);
+  AdjArgs a{pv, fp, P, w, nmax, t_begin, t_end};
+  const size_t shm = adjoint_lds_bytes(nmax, fp.grid_s, fp.n_steps, fp.precision);
   if (fp.precision == 0) {
-    if (fp.profile == 0) hipLaunchKernelGGL((k_adjoint<0, true>), dim3(grid), dim3(kTileBlock), shm, s, a);
-    else hipLaunchKernelGGL((k_adjoint<0, false>), dim3(grid), dim3(kTileBlock), shm, s, a);
+    if (stored) {
+      if (fp.profile == 0) hipLaunchKernelGGL((k_adjoint<0, true, true>), dim3(grid), dim3(kTileBlock), shm, s, a);
+      else hipLaunchKernelGGL((k_adjoint<0, false, true>), dim3(grid), dim3(kTileBlock), shm, s, a);
+    } else {
+      if (fp.profile == 0) hipLaunchKernelGGL((k_adjoint<0, true, false>), dim3(grid), dim3(kTileBlock), shm, s, a);
+      else hipLaunchKernelGGL((k_adjoint<0, false, false>), dim3(grid), dim3(kTileBlock), shm, s, a);
+    }
   } else {
-    if (fp.profile == 0) hipLaunchKernelGGL((k_adjoint<1, true>), dim3(grid), dim3(kTileBlock), shm, s, a);
-    else hipLaunchKernelGGL((k_adjoint<1, false>), dim3(grid), dim3(kTileBlock), shm, s, a);
+    if (stored) return hipErrorInvalidValue;  // S is stored by the FP32 form only
+    if (fp.profile == 0) hipLaunchKernelGGL((k_adjoint<1, true, false>), dim3(grid), dim3(kTileBlock), shm, s, a);
+    else hipLaunchKernelGGL((k_adjoint<1, false, false>), dim3(grid), dim3(kTileBlock), shm, s, a);
   }
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  if (mid_event) (void)hipEventRecord(mid_event, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_finish(const PlanView& pv, const FibreParams& fp, const double* P, const Work& w,
+                              double* coef, double* dthr, hipStream_t s) {
+  const int M = fp.n_steps;
   if (fp.profile == 0) {
     hipLaunchKernelGGL(k_cf_adj_rows, dim3(M + 1, pv.n_batch), dim3(256), 0, s, pv, fp, P, w, coef);
     hipLaunchKernelGGL(k_cf_adj_channels, dim3((pv.n_total + 255) / 256), dim3(256), 0, s, pv, fp, w,
@@ -593,5 +621,6 @@ hipError_t launch_grad(const PlanView& pv, const FibreParams& fp, const double* 
   hipLaunchKernelGGL(k_grad_final, dim3((pv.n_total + 255) / 256), dim3(256), 0, s, pv, w, dthr);
   return hipGetLastError();
 }
+
 
 }  // namespace isrsgn

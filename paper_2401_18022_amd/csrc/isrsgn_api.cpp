@@ -86,6 +86,11 @@ struct PlanEntry {
   DevBuf abar, zm, dz, hdz32, ell64, lt32, ellL, tiles, pnli, snr, counter;
   DevBuf states, state_off, lam, gG, gL, gLL, gP, coef;
   bool grad_ready = false;
+  // FP32 gradient: row batches whose per-node S fits the store (see ensure_grad_workspace)
+  struct RowBatch { unsigned int t0, t1; int g0, g1; };
+  std::vector<RowBatch> batches;
+  DevBuf s_store;
+  bool store_ok = false;
   // graph mode: owned inputs/outputs and the instantiated graphs
   DevBuf g_P, g_nf, g_a, g_b, g_c, g_thr;
   std::vector<GraphEntry> graphs;
@@ -144,10 +149,12 @@ struct isrsgn_fibre {
   FibreParams fp{};
   int device = 0, n_cu = 0;
   std::vector<std::unique_ptr<PlanEntry>> plans;  // most recent first
+  // timing (isrsgn_set_timing): events recorded by the last call and the stage spans between them
   bool timing = false;
-  hipEvent_t ev[7] = {};
-  bool ev_used[7] = {};
-  bool ev_ready = false;
+  std::vector<hipEvent_t> evs;
+  int ev_count = 0;
+  struct Span { int stage, a, b; };
+  std::vector<Span> spans;
 };
 
 namespace {
@@ -261,10 +268,26 @@ int get_plan(isrsgn_fibre* h, const isrsgn_plan* p, hipStream_t s, PlanEntry** o
   return ISRSGN_OK;
 }
 
-void record(isrsgn_fibre* h, int slot, hipStream_t s) {
-  if (!h->timing || !h->ev_ready) return;
-  (void)hipEventRecord(h->ev[slot], s);
-  h->ev_used[slot] = true;
+// Timing: each call starts a new list of events; stages 0 steps + profile, 1 forward tiles,
+// 2 reductions, 3 adjoint tiles, 4 rest of the gradient (summed over row batches).
+void begin_timing(isrsgn_fibre* h) {
+  h->ev_count = 0;
+  h->spans.clear();
+}
+
+int mark(isrsgn_fibre* h, hipStream_t s) {
+  if (!h->timing) return -1;
+  if (h->ev_count == (int)h->evs.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return -1;
+    h->evs.push_back(e);
+  }
+  if (hipEventRecord(h->evs[h->ev_count], s) != hipSuccess) return -1;
+  return h->ev_count++;
+}
+
+void add_span(isrsgn_fibre* h, int stage, int a, int b) {
+  if (a >= 0 && b >= 0) h->spans.push_back({stage, a, b});
 }
 
 int tile_grid(isrsgn_fibre* h, const PlanEntry* e, int variant, int64_t tiles) {
@@ -330,7 +353,7 @@ int pick_variant(isrsgn_fibre* h, PlanEntry* e, const double* P, const Work& w, 
   for (int v = 0; v < kTileVariants && err == hipSuccess; ++v) {
     for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {
       (void)hipEventRecord(a, s);
-      err = launch_tiles(pv, h->fp, P, w, e->nmax, tile_grid(h, e, v, trial), v, begin, end, s);
+      err = launch_tiles(pv, h->fp, P, w, e->nmax, tile_grid(h, e, v, trial), v, begin, end, true, s);
       (void)hipEventRecord(b, s);
       if (err == hipSuccess) err = hipEventSynchronize(b);
       float ms = 0.f;
@@ -356,29 +379,42 @@ int pick_variant(isrsgn_fibre* h, PlanEntry* e, const double* P, const Work& w, 
   return ISRSGN_OK;
 }
 
-// Steps, profile, pair integrals and reduction.  Outputs may be NULL.
-int forward(isrsgn_fibre* h, PlanEntry* e, const double* P, const double* nf, double snr_trx, double* eta,
-            double* pnli, double* tiles_out, double* snr, double* thr, bool keep_states, hipStream_t s) {
-  for (int q = 0; q < 7; ++q) h->ev_used[q] = false;
-  record(h, 0, s);
-  Work w = e->work();
-  if (tiles_out) w.tiles = tiles_out;
-  PlanView pv = e->view();
+// Steps, profile and the tile-kernel variant: the first timing stage.  *mk gets its end mark.
+int prologue(isrsgn_fibre* h, PlanEntry* e, const double* P, const Work& w, bool keep_states, hipStream_t s,
+             int* variant, int* mk) {
+  begin_timing(h);
+  const int m0 = mark(h, s);
+  const PlanView pv = e->view();
   hipError_t err;
   if ((err = launch_steps(pv, h->fp, P, w, s)) != hipSuccess) return hip_fail(err, "steps");
   if ((err = launch_profile(pv, h->fp, P, w, keep_states, s)) != hipSuccess) return hip_fail(err, "profile");
-  int variant = 0;
-  int rc = pick_variant(h, e, P, w, pv, s, &variant);
+  const int rc = pick_variant(h, e, P, w, pv, s, variant);
   if (rc) return rc;
-  h->last_variant = variant;
-  record(h, 1, s);
+  h->last_variant = *variant;
+  *mk = mark(h, s);
+  add_span(h, 0, m0, *mk);
+  return ISRSGN_OK;
+}
+
+// Steps, profile, pair integrals and reduction.  Outputs may be NULL.  *mk gets the end mark.
+int forward(isrsgn_fibre* h, PlanEntry* e, const double* P, const double* nf, double snr_trx, double* eta,
+            double* pnli, double* tiles_out, double* snr, double* thr, bool keep_states, hipStream_t s, int* mk) {
+  Work w = e->work();
+  if (tiles_out) w.tiles = tiles_out;
+  const PlanView pv = e->view();
+  int variant = 0, m1 = -1;
+  const int rc = prologue(h, e, P, w, keep_states, s, &variant, &m1);
+  if (rc) return rc;
+  hipError_t err;
   if ((err = launch_tiles(pv, h->fp, P, w, e->nmax, tile_grid(h, e, variant, e->n_tiles), variant, 0u,
-                          (unsigned int)e->n_tiles, s)) != hipSuccess)
+                          (unsigned int)e->n_tiles, true, s)) != hipSuccess)
     return hip_fail(err, "pair integrals");
-  record(h, 2, s);
+  const int m2 = mark(h, s);
+  add_span(h, 1, m1, m2);
   if ((err = launch_reduce(pv, h->fp, P, nf, snr_trx, w, eta, pnli, snr, thr, s)) != hipSuccess)
     return hip_fail(err, "reduction");
-  record(h, 3, s);
+  *mk = mark(h, s);
+  add_span(h, 2, m2, *mk);
   return ISRSGN_OK;
 }
 
@@ -403,25 +439,111 @@ int ensure_grad_workspace(isrsgn_fibre* h, PlanEntry* e) {
   if (!ok) return fail(ISRSGN_ENOMEM, "device allocation failed for the adjoint workspace");
   hipError_t err = hipMemcpy(e->state_off.p, soff.data(), 8 * (nb + 1), hipMemcpyHostToDevice);
   if (err != hipSuccess) return hip_fail(err, "state offsets");
+  // FP32 form: the forward pass keeps S of every node for the adjoint, one batch of complete
+  // COI rows at a time (a row's SNR, and so its upstream weight, needs only that row).  The
+  // store is bounded by ISRSGN_STORE_MB (default 16384 MiB; 0 disables it); when a row does not
+  // fit or the allocation fails, the adjoint recomputes S instead.
+  e->batches.clear();
+  e->store_ok = false;
+  const char* env = std::getenv("ISRSGN_STORE_MB");
+  const double store_mb = env && *env ? std::atof(env) : 16384.0;
+  const int64_t per_tile = (int64_t)3 * h->desc.grid_s * h->desc.grid_v * (int64_t)sizeof(float2);
+  const int64_t max_tiles = h->desc.precision == ISRSGN_FP32 && store_mb > 0
+                                ? (int64_t)(store_mb * 1048576.0 / (double)per_tile) : 0;
+  bool fits = max_tiles > 0;
+  for (size_t b = 0; b < nb && fits; ++b) fits = e->off[b + 1] - e->off[b] <= max_tiles;
+  if (fits) {
+    int64_t t = 0, t0 = 0, cnt = 0, most = 0;
+    int g0 = 0;
+    for (size_t b = 0; b < nb; ++b) {
+      const int n = e->off[b + 1] - e->off[b];
+      for (int i = 0; i < n; ++i) {
+        const int g = e->off[b] + i;  // global channel of this COI row
+        if (cnt + n > max_tiles && cnt > 0) {
+          e->batches.push_back({(unsigned int)t0, (unsigned int)t, g0, g});
+          most = std::max(most, cnt);
+          t0 = t;
+          g0 = g;
+          cnt = 0;
+        }
+        t += n;
+        cnt += n;
+      }
+    }
+    e->batches.push_back({(unsigned int)t0, (unsigned int)t, g0, e->n_total});
+    most = std::max(most, cnt);
+    e->store_ok = e->s_store.ensure((size_t)(most * per_tile));
+    if (!e->store_ok) e->batches.clear();
+  }
   e->grad_ready = true;
+  return ISRSGN_OK;
+}
+
+// Gradient with the per-node S store: per row batch, forward tiles (keeping S), the batch's
+// P_NLI, SNR and upstream weights, then its adjoint tiles; then throughput and profile adjoint.
+int enqueue_grad_stored(isrsgn_fibre* h, PlanEntry* e, const double* P, const double* nf, double snr_trx,
+                        double* snr, double* thr, double* dthr, hipStream_t s) {
+  Work w = e->work();
+  const PlanView pv = e->view();
+  int variant = 0, mk = -1;
+  const int rc = prologue(h, e, P, w, h->desc.profile == ISRSGN_PROFILE_ODE, s, &variant, &mk);
+  if (rc) return rc;
+  w.s_store = e->s_store.as<float2>();
+  hipError_t err = launch_grad_init(pv, h->fp, w, s);
+  if (err != hipSuccess) return hip_fail(err, "adjoint");
+  const int adj_per_cu = adjoint_blocks_per_cu(h->fp, e->nmax, true);
+  bool first = true;
+  for (const auto& bt : e->batches) {
+    const int64_t nt = (int64_t)bt.t1 - bt.t0;
+    if ((err = launch_tiles(pv, h->fp, P, w, e->nmax, tile_grid(h, e, variant, nt), variant, bt.t0, bt.t1, first,
+                            s)) != hipSuccess)
+      return hip_fail(err, "pair integrals");
+    first = false;
+    const int ma = mark(h, s);
+    add_span(h, 1, mk, ma);
+    err = launch_reduce_rows(pv, P, nf, snr_trx, w, nullptr, nullptr, snr, bt.g0, bt.g1, s);
+    if (err == hipSuccess) err = launch_grad_rows(pv, P, nf, snr_trx, w, bt.g0, bt.g1, s);
+    if (err != hipSuccess) return hip_fail(err, "reduction");
+    const int mb = mark(h, s);
+    add_span(h, 2, ma, mb);
+    const int64_t grid = std::min<int64_t>((int64_t)adj_per_cu * h->n_cu, nt);
+    if ((err = launch_adjoint_tiles(pv, h->fp, P, w, e->nmax, (int)(grid < 1 ? 1 : grid), bt.t0, bt.t1, true, s)) !=
+        hipSuccess)
+      return hip_fail(err, "adjoint");
+    mk = mark(h, s);
+    add_span(h, 3, mb, mk);
+  }
+  if ((err = launch_throughput(pv, P, w, thr, s)) != hipSuccess) return hip_fail(err, "throughput");
+  if ((err = launch_grad_finish(pv, h->fp, P, w, e->coef.as<double>(), dthr, s)) != hipSuccess)
+    return hip_fail(err, "adjoint");
+  add_span(h, 4, mk, mark(h, s));
   return ISRSGN_OK;
 }
 
 // The whole sequence of one call, enqueued on s.
 int enqueue_call(isrsgn_fibre* h, PlanEntry* e, int kind, const double* P, const double* nf, double snr_trx,
                  double* eta, double* pnli, double* tiles, double* snr, double* thr, double* dthr, hipStream_t s) {
+  if (kind == kGrad && e->store_ok) return enqueue_grad_stored(h, e, P, nf, snr_trx, snr, thr, dthr, s);
+  int m3 = -1;
   int rc = forward(h, e, P, nf, snr_trx, eta, pnli, tiles, snr, thr,
-                   kind == kGrad && h->desc.profile == ISRSGN_PROFILE_ODE, s);
+                   kind == kGrad && h->desc.profile == ISRSGN_PROFILE_ODE, s, &m3);
   if (rc || kind != kGrad) return rc;
-  const int per_cu = adjoint_blocks_per_cu(h->fp, e->nmax);
+  const int per_cu = adjoint_blocks_per_cu(h->fp, e->nmax, false);
   int64_t grid = (int64_t)per_cu * h->n_cu;
   if (grid > e->n_tiles) grid = e->n_tiles;
-  hipEvent_t mid = (h->timing && h->ev_ready) ? h->ev[4] : nullptr;
-  if (mid) h->ev_used[4] = true;
-  hipError_t err = launch_grad(e->view(), h->fp, P, nf, snr_trx, e->work(), e->nmax, (int)(grid < 1 ? 1 : grid),
-                               e->coef.as<double>(), dthr, s, mid);
+  const Work w = e->work();
+  const PlanView pv = e->view();
+  hipError_t err = launch_grad_init(pv, h->fp, w, s);
+  if (err == hipSuccess) err = launch_grad_rows(pv, P, nf, snr_trx, w, 0, pv.n_total, s);
+  if (err == hipSuccess)
+    err = launch_adjoint_tiles(pv, h->fp, P, w, e->nmax, (int)(grid < 1 ? 1 : grid), 0u, (unsigned int)e->n_tiles,
+                               false, s);
   if (err != hipSuccess) return hip_fail(err, "adjoint");
-  record(h, 5, s);
+  const int m4 = mark(h, s);
+  add_span(h, 3, m3, m4);
+  if ((err = launch_grad_finish(pv, h->fp, P, w, e->coef.as<double>(), dthr, s)) != hipSuccess)
+    return hip_fail(err, "adjoint");
+  add_span(h, 4, m4, mark(h, s));
   return ISRSGN_OK;
 }
 
@@ -476,8 +598,8 @@ int run_graph(isrsgn_fibre* h, PlanEntry* e, int kind, const double* P, const do
     e->graphs.push_back(GraphEntry{kind, snr_trx, exec});
     ge = &e->graphs.back();
   }
-  for (int q = 0; q < 7; ++q) h->ev_used[q] = false;
-  record(h, 0, s);
+  begin_timing(h);
+  mark(h, s);
   hipError_t err = launch_copy(e->g_P.as<double>(), P, (int64_t)nt, s);
   if (err == hipSuccess && nf) err = launch_copy(e->g_nf.as<double>(), nf, (int64_t)nt, s);
   if (err == hipSuccess) err = hipGraphLaunch(ge->exec, s);
@@ -493,7 +615,7 @@ int run_graph(isrsgn_fibre* h, PlanEntry* e, int kind, const double* P, const do
     }
   }
   if (err != hipSuccess) return hip_fail(err, "graph launch");
-  record(h, 5, s);
+  mark(h, s);
   return ISRSGN_OK;
 }
 
@@ -627,13 +749,6 @@ int isrsgn_profile(isrsgn_fibre* h, const isrsgn_plan* plan, const double* P, do
 int isrsgn_set_timing(isrsgn_fibre* h, int enabled) {
   g_err.clear();
   if (!h) return fail(ISRSGN_EINVAL, "handle is NULL");
-  if (enabled && !h->ev_ready) {
-    for (int q = 0; q < 7; ++q) {
-      hipError_t err = hipEventCreate(&h->ev[q]);
-      if (err != hipSuccess) return hip_fail(err, "hipEventCreate");
-    }
-    h->ev_ready = true;
-  }
   h->timing = enabled != 0;
   return ISRSGN_OK;
 }
@@ -642,19 +757,16 @@ int isrsgn_stage_times(isrsgn_fibre* h, double* ms, int n) {
   g_err.clear();
   if (!h || !ms || n < 1) return fail(ISRSGN_EINVAL, "handle and output are required");
   for (int q = 0; q < n && q < 6; ++q) ms[q] = 0.0;
-  if (!h->ev_ready) return ISRSGN_OK;
-  int last = -1;
-  for (int q = 0; q < 7; ++q) if (h->ev_used[q]) last = q;
-  if (last < 0) return ISRSGN_OK;
-  hipError_t err = hipEventSynchronize(h->ev[last]);
+  if (h->ev_count < 1) return ISRSGN_OK;
+  hipError_t err = hipEventSynchronize(h->evs[h->ev_count - 1]);
   if (err != hipSuccess) return hip_fail(err, "hipEventSynchronize");
-  auto span = [&](int a, int b) -> double {
-    if (!h->ev_used[a] || !h->ev_used[b]) return 0.0;
+  auto elapsed = [&](int a, int b) -> double {
     float t = 0.f;
-    return hipEventElapsedTime(&t, h->ev[a], h->ev[b]) == hipSuccess ? (double)t : 0.0;
+    return hipEventElapsedTime(&t, h->evs[a], h->evs[b]) == hipSuccess ? (double)t : 0.0;
   };
-  // events: 0 start, 1 after profile, 2 after tiles, 3 after reduce, 4 after adjoint tiles, 5 end of gradient
-  const double st[6] = {span(0, 1), span(1, 2), span(2, 3), span(3, 4), span(4, 5), span(0, last)};
+  double st[6] = {0, 0, 0, 0, 0, 0};
+  for (const auto& sp : h->spans) st[sp.stage] += elapsed(sp.a, sp.b);
+  st[5] = elapsed(0, h->ev_count - 1);
   for (int q = 0; q < n && q < 6; ++q) ms[q] = st[q];
   return ISRSGN_OK;
 }
@@ -677,8 +789,7 @@ int isrsgn_work_counts(isrsgn_fibre* h, double* out, int n) {
 void isrsgn_destroy(isrsgn_fibre* h) {
   if (!h) return;
   (void)hipDeviceSynchronize();
-  if (h->ev_ready)
-    for (int q = 0; q < 7; ++q) (void)hipEventDestroy(h->ev[q]);
+  for (hipEvent_t ev : h->evs) (void)hipEventDestroy(ev);
   h->plans.clear();
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   delete h;

@@ -359,6 +359,8 @@ struct StepLds {
   double zm;   // step midpoint z_m
   float hdz;   // dz_m / 2
   float zmf;   // z_m in FP32 (small-phase tier)
+  float dz;    // dz_m
+  float c2;    // (2 pi dz_m / 2)^2: the sinc argument squared is phr^2 c2
 };
 
 // Per-tile table columns for the f3 and f_i terms of E_m, staged in LDS.  f3 lies in channel k,
@@ -371,7 +373,7 @@ struct Col4 {
 
 struct Term32 {
   double phr;
-  float phrf, inv_piphr, t1, t2, t3;
+  float phrf, phrf2, inv_piphr, t1, t2, t3;
   unsigned o1, o2;  // byte offsets of the f1 / f2 segments within a table row
   bool up3;         // f3 uses segment B
 };
@@ -380,6 +382,7 @@ __device__ inline Term32 term32_setup(const Node& nd, int k, int n) {
   Term32 q;
   q.phr = nd.phr;
   q.phrf = (float)nd.phr;
+  q.phrf2 = q.phrf * q.phrf;
   q.inv_piphr = 1.0f / ((float)kPi * q.phrf);
   q.t1 = (float)nd.t1;
   q.t2 = (float)nd.t2;
@@ -422,6 +425,9 @@ __device__ inline void load_steps(StepLds* st, const double* __restrict__ zm, co
     v.zm = zm[m];
     v.hdz = hdz[m];
     v.zmf = (float)zm[m];
+    v.dz = 2.0f * hdz[m];
+    const float c = 2.0f * (float)kPi * hdz[m];
+    v.c2 = c * c;
     st[m] = v;
   }
 }
@@ -461,24 +467,27 @@ __device__ inline float2 term32(const Term32& q, int m, const StepLds* __restric
   const float2 cab = reinterpret_cast<const float2*>(col + m)[q.up3 ? 1 : 0];
   float fr;
   if (kTier == kTierSmall) {
-    const float tt = q.phrf * sv.zmf;
-    fr = tt - rintf(tt);
+    fr = q.phrf * sv.zmf;  // |phr z_m| < 1/4 at every step of this tier: already reduced
   } else {
-    const double tt = q.phr * sv.zm;
-    fr = (float)(tt - rint(tt));
+    // fract(phr z_m + 1/2) - 1/2 lies in [-1/2, 1/2): one FMA, fract and convert in FP64
+    fr = (float)__builtin_amdgcn_fract(fma(q.phr, sv.zm, 0.5)) - 0.5f;
   }
   const float sn = __builtin_amdgcn_sinf(fr);
   const float cs = __builtin_amdgcn_cosf(fr);
-  const float hh = q.phrf * sv.hdz;
+  // Amplitude dz_m sinc(phi dz_m / 2).  The large tier returns sin(phi dz_m / 2) without the
+  // per-node factor 1 / (pi phr): its callers apply that factor once per node.
   float amp0;
   if (kTier != kTierLarge) {
-    const float u = 2.0f * (float)kPi * hh;
-    const float u2 = u * u;
-    const float dzm = 2.0f * sv.hdz;
-    amp0 = dzm * (1.0f + u2 * (-1.0f / 6.0f + u2 * (1.0f / 120.0f - u2 * (1.0f / 5040.0f))));
-    if (kTier == kTierMixed && !(fabsf(u) < 0.5f)) amp0 = __builtin_amdgcn_sinf(hh - rintf(hh)) * q.inv_piphr;
+    const float u2 = q.phrf2 * sv.c2;
+    amp0 = sv.dz * fmaf(u2, fmaf(u2, fmaf(u2, -1.0f / 5040.0f, 1.0f / 120.0f), -1.0f / 6.0f), 1.0f);
+    if (kTier == kTierMixed) {  // both forms, then a per-lane select (no branch)
+      const float hh = q.phrf * sv.hdz;
+      const float as = __builtin_amdgcn_sinf(hh - rintf(hh)) * q.inv_piphr;
+      amp0 = u2 < 0.25f ? amp0 : as;
+    }
   } else {
-    amp0 = __builtin_amdgcn_sinf(hh - rintf(hh)) * q.inv_piphr;
+    const float hh = q.phrf * sv.hdz;
+    amp0 = __builtin_amdgcn_sinf(hh - rintf(hh));
   }
   const float e3 = fmaf(q.t3, cab.y, cab.x);
   float e2;
@@ -507,13 +516,6 @@ __device__ inline int wave_tier(bool small, bool large) {
   return kTierMixed;
 }
 
-template <bool kLinear>
-__device__ inline float2 term32_tier(int tier, const Term32& q, int m, const StepLds* __restrict__ st,
-                                     const Col4* __restrict__ col, const Tab32& tab, int n) {
-  if (tier == kTierSmall) return term32<kLinear, kTierSmall>(q, m, st, col, tab, n);
-  if (tier == kTierLarge) return term32<kLinear, kTierLarge>(q, m, st, col, tab, n);
-  return term32<kLinear, kTierMixed>(q, m, st, col, tab, n);
-}
 
 // S = sum of the step terms of one node at a fixed tier.
 template <bool kLinear, int kTier, int kUnroll>
@@ -525,6 +527,10 @@ __device__ inline void accumulate32(const Term32& q, const StepLds* __restrict__
     const float2 t = term32<kLinear, kTier>(q, m, st, col, tab, n);
     a += t.x;
     b += t.y;
+  }
+  if (kTier == kTierLarge) {
+    a *= q.inv_piphr;
+    b *= q.inv_piphr;
   }
   *sr = a;
   *si = b;

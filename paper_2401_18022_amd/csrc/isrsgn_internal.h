@@ -52,6 +52,9 @@ struct Work {
   double* snr;      // [n_total]
   unsigned int* counter;  // work counter of the persistent tile kernels
   unsigned long long* nodes;  // nodes evaluated by the last forward tile launch
+  // FP32 form with a gradient: S of every node of the current row batch, written by the
+  // forward tile kernel and read by the adjoint ([tile - t_begin][part][node]), or null
+  float2* s_store;
   // adjoint
   double* states;   // ODE states, plan b at sstate_off[b]: [(M*2*ode_sub + 1) * N_b]
   const int64_t* state_off;
@@ -67,19 +70,33 @@ hipError_t launch_channel_setup(const PlanView& pv, const FibreParams& fp, hipSt
 hipError_t launch_steps(const PlanView& pv, const FibreParams& fp, const double* P, const Work& w, hipStream_t s);
 hipError_t launch_profile(const PlanView& pv, const FibreParams& fp, const double* P, const Work& w,
                           bool keep_states, hipStream_t s);
+// tiles [t_begin, t_end); reset_nodes clears the evaluated-node counter first (a call's first launch)
 hipError_t launch_tiles(const PlanView& pv, const FibreParams& fp, const double* P, const Work& w,
-                        int nmax, int grid, int variant, unsigned int t_begin, unsigned int t_end, hipStream_t s);
+                        int nmax, int grid, int variant, unsigned int t_begin, unsigned int t_end, bool reset_nodes,
+                        hipStream_t s);
 const char* tile_variant_name(int variant);
 hipError_t launch_reduce(const PlanView& pv, const FibreParams& fp, const double* P, const double* nf,
                          double snr_trx, const Work& w, double* eta, double* pnli_out, double* snr_out,
                          double* thr_out, hipStream_t s);
+// P_NLI, eta and SNR of the global channels [g_begin, g_end) (their tile rows must be complete)
+hipError_t launch_reduce_rows(const PlanView& pv, const double* P, const double* nf, double snr_trx, const Work& w,
+                              double* eta, double* pnli_out, double* snr_out, int g_begin, int g_end,
+                              hipStream_t s);
+hipError_t launch_throughput(const PlanView& pv, const double* P, const Work& w, double* thr_out, hipStream_t s);
 hipError_t launch_copy_profile(const PlanView& pv, const FibreParams& fp, const Work& w, double* zm,
                                double* dz, double* ell, double* ellL, hipStream_t s);
-hipError_t launch_grad(const PlanView& pv, const FibreParams& fp, const double* P, const double* nf,
-                       double snr_trx, const Work& w, int nmax, int grid, double* coef, double* dthr,
-                       hipStream_t s, hipEvent_t mid_event);
+// The gradient in pieces (row batches): clear dT/d ell and dT/dG; upstream weights of the
+// channels [g_begin, g_end); the adjoint of tiles [t_begin, t_end) (stored: S comes from
+// w.s_store instead of a recomputing sweep, FP32 form only); profile adjoint and assembly.
+hipError_t launch_grad_init(const PlanView& pv, const FibreParams& fp, const Work& w, hipStream_t s);
+hipError_t launch_grad_rows(const PlanView& pv, const double* P, const double* nf, double snr_trx, const Work& w,
+                            int g_begin, int g_end, hipStream_t s);
+hipError_t launch_adjoint_tiles(const PlanView& pv, const FibreParams& fp, const double* P, const Work& w, int nmax,
+                                int grid, unsigned int t_begin, unsigned int t_end, bool stored, hipStream_t s);
+hipError_t launch_grad_finish(const PlanView& pv, const FibreParams& fp, const double* P, const Work& w,
+                              double* coef, double* dthr, hipStream_t s);
 size_t adjoint_lds(int nmax, int gs, int M, int prec);
-int adjoint_blocks_per_cu(const FibreParams& fp, int nmax);
+int adjoint_blocks_per_cu(const FibreParams& fp, int nmax, bool stored);
 int tile_blocks_per_cu(const FibreParams& fp, int nmax, int variant);
 hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
 

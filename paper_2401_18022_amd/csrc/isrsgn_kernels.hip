@@ -241,6 +241,7 @@ k_tiles(TileArgs A) {
           else if (tier == kTierLarge) accumulate32<kLinear, kTierLarge, kUnroll>(tq, steps, col, tab, n, M, &sr, &si);
           else accumulate32<kLinear, kTierMixed, kUnroll>(tq, steps, col, tab, n, M, &sr, &si);
           s2v = (double)sr * sr + (double)si * si;
+          if (A.w.s_store) A.w.s_store[((int64_t)(t - A.t_begin) * 3 + part) * nodes + q] = make_float2(sr, si);
         } else {
           const Term64 tq = term64_setup(nd, i);
           const double* tab = A.w.ell64 + (size_t)M * o;
@@ -270,16 +271,16 @@ k_tiles(TileArgs A) {
 
 __global__ void k_zero_counter(unsigned int* c, unsigned long long* nodes) {
   *c = 0u;
-  *nodes = 0ull;
+  if (nodes) *nodes = 0ull;
 }
 
 // ---------------------------------------------------------------------------- reduction
 // One wave per channel: P_NLI,i = 16/27 gamma_i^2 R_i sum_k tile(i,k) (eq. gain_fin times R_i),
 // eta_i = P_NLI,i / P_i^3, P_ASE,i = NF_i h f_i R_i / rho(L, f_i), SNR_i (eq. loss).
 __global__ void k_reduce(PlanView pv, const double* __restrict__ P, const double* __restrict__ nf, double snr_trx,
-                         Work w, double* eta, double* pnli_out, double* snr_out) {
-  const int g = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (g >= pv.n_total) return;
+                         Work w, double* eta, double* pnli_out, double* snr_out, int g_begin, int g_end) {
+  const int g = g_begin + blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (g >= g_end) return;
   const int b = plan_of_channel(pv, g), o = pv.off[b], n = pv.off[b + 1] - o, i = g - o;
   const double* row = w.tiles + pv.toff[b] + (int64_t)i * n;
   double s = 0.0;
@@ -401,8 +402,9 @@ int tile_blocks_per_cu(const FibreParams& fp, int nmax, int variant) {
 }
 
 hipError_t launch_tiles(const PlanView& pv, const FibreParams& fp, const double* P, const Work& w, int nmax,
-                        int grid, int variant, unsigned int t_begin, unsigned int t_end, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, w.counter, w.nodes);
+                        int grid, int variant, unsigned int t_begin, unsigned int t_end, bool reset_nodes,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, w.counter, reset_nodes ? w.nodes : nullptr);
   TileArgs a{pv, fp, P, w, nmax, t_begin, t_end};
   const size_t shm = tile_lds_bytes(nmax, fp.grid_s, fp.n_steps);
   void* args[] = {&a};
@@ -412,16 +414,27 @@ hipError_t launch_tiles(const PlanView& pv, const FibreParams& fp, const double*
   return hipGetLastError();
 }
 
+hipError_t launch_reduce_rows(const PlanView& pv, const double* P, const double* nf, double snr_trx, const Work& w,
+                              double* eta, double* pnli_out, double* snr_out, int g_begin, int g_end,
+                              hipStream_t s) {
+  if (g_end <= g_begin) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce, dim3((g_end - g_begin + 3) / 4), dim3(256), 0, s, pv, P, nf, snr_trx, w, eta,
+                     pnli_out, snr_out, g_begin, g_end);
+  return hipGetLastError();
+}
+
+hipError_t launch_throughput(const PlanView& pv, const double* P, const Work& w, double* thr_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_throughput, dim3(pv.n_batch), dim3(256), 0, s, pv, P, w, thr_out);
+  return hipGetLastError();
+}
+
 hipError_t launch_reduce(const PlanView& pv, const FibreParams& fp, const double* P, const double* nf,
                          double snr_trx, const Work& w, double* eta, double* pnli_out, double* snr_out,
                          double* thr_out, hipStream_t s) {
   (void)fp;
-  hipLaunchKernelGGL(k_reduce, dim3((pv.n_total + 3) / 4), dim3(256), 0, s, pv, P, nf, snr_trx, w, eta, pnli_out,
-                     snr_out);
-  hipError_t e = hipGetLastError();
+  hipError_t e = launch_reduce_rows(pv, P, nf, snr_trx, w, eta, pnli_out, snr_out, 0, pv.n_total, s);
   if (e != hipSuccess || !thr_out) return e;
-  hipLaunchKernelGGL(k_throughput, dim3(pv.n_batch), dim3(256), 0, s, pv, P, w, thr_out);
-  return hipGetLastError();
+  return launch_throughput(pv, P, w, thr_out, s);
 }
 
 hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s) {
