@@ -29,6 +29,10 @@ sys.path.insert(0, ROOT)
 # "Roofline"): 4 transcendentals (sin, cos of the phase, sin of the sinc, exp of the power
 # term) at a quarter of the FP32 rate = 16 slots, plus 14 single-rate FP32 operations.
 SLOTS_PER_NODE_STEP = 30
+# The adjoint, per node-step: the step term again (30), Q_m = c Re(conj(S) term_m) (3) and its
+# five weighted sums over nodes (sum q, q t1, q t2, q w3a, q w3c: 5).  When it has to recompute
+# S (no per-node store), another 30.
+ADJ_SLOTS_PER_NODE_STEP = 38
 FLOP_EQ_PER_SLOT = 2            # one FMA slot = 2 FLOP at the FP32 vector peak
 PEAK_FP32_TFLOPS = 157.3        # MI355X FP32 vector (no matrix cores)
 
@@ -151,11 +155,13 @@ def main():
     ms_step = 1e3 * elapsed / args.steps
     tiles_ms = stages["tiles"] / args.steps
     node_steps = work["node_steps"]
-    # the adjoint sweeps every node's steps twice (S, then each term's share of dT/dE_m)
-    dominant, dom_ms, dom_sweeps = "pair_integral_forward", tiles_ms, 1
+    dominant, dom_ms, dom_slots = "pair_integral_forward", tiles_ms, SLOTS_PER_NODE_STEP
     if grad and stages["adjoint_tiles"] / args.steps > tiles_ms:
-        dominant, dom_ms, dom_sweeps = "pair_integral_adjoint", stages["adjoint_tiles"] / args.steps, 2
-    achieved = dom_sweeps * node_steps * SLOTS_PER_NODE_STEP * FLOP_EQ_PER_SLOT / (dom_ms * 1e-3) / 1e12
+        dominant, dom_ms = "pair_integral_adjoint", stages["adjoint_tiles"] / args.steps
+        dom_slots = ADJ_SLOTS_PER_NODE_STEP + (0 if work["grad_batches"] > 0 else SLOTS_PER_NODE_STEP)
+    # stage times are sums over the call's launches of the kernel (one per batch of COI rows)
+    launches = max(1, work["grad_batches"]) if grad else 1
+    achieved = node_steps * dom_slots * FLOP_EQ_PER_SLOT / (dom_ms * 1e-3) / 1e12
     rec = recorded_traffic(dominant, args.grid)
 
     fp64 = None
@@ -208,8 +214,9 @@ def main():
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": (rec[0] + rec[1]) if rec else None,
                      "traffic_fetch_write_bytes": [rec[0], rec[1]] if rec else None,
                      "traffic_source": rec[2] if rec else None, "kernel": dominant,
-                     "kernel_ms": dom_ms, "node_steps_per_launch": dom_sweeps * node_steps,
-                     "slots_per_node_step": SLOTS_PER_NODE_STEP, "tile_variant": work["variant"]},
+                     "kernel_ms_per_step": dom_ms, "launches_per_step": launches,
+                     "node_steps_per_step": node_steps, "slots_per_node_step": dom_slots,
+                     "tile_variant": work["variant"]},
         "cpu_baseline": cpu,
         "stages_ms": {k: v / args.steps for k, v in stages.items()},
         "snr_wall_ms": (stages["profile"] + stages["tiles"] + stages["reduce"]) / args.steps,

@@ -147,11 +147,14 @@ int isrsgn_set_graph(isrsgn_fibre* h, int enabled);
 int isrsgn_set_timing(isrsgn_fibre* h, int enabled);
 int isrsgn_stage_times(isrsgn_fibre* h, double* ms_out, int n);
 
-/* Work done by the last forward pair-integral launch on the most recently used plan
+/* Work done by the last call's forward pair integrals on the most recently used plan
  * (waits for it): [0] nodes evaluated (nodes on the channel support of non-empty rows),
  * [1] node-steps = nodes * n_steps, [2] tiles, [3] index of the tile-kernel variant the
  * autotuner chose (ISRSGN_TILE_VARIANT in the environment forces one; ISRSGN_TUNE_CACHE
- * names a file that keeps the choices across processes).  n is the capacity of out (up to 4). */
+ * names a file that keeps the choices across processes), [4] batches of COI rows of an FP32
+ * gradient with the per-node store (0: the adjoint recomputed S; the store is bounded by
+ * ISRSGN_STORE_MB in the environment, default 16384 MiB, 0 disables it).  n is the capacity of
+ * out (up to 5). */
 int isrsgn_work_counts(isrsgn_fibre* h, double* out, int n);
 
 /* Frees the handle and its device memory (waits for its outstanding work).  NULL is allowed. */

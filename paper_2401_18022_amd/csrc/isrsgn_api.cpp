@@ -141,6 +141,7 @@ struct PlanEntry {
 
 struct isrsgn_fibre {
   int last_variant = -1;
+  int last_grad_batches = 0;  // row batches of the last gradient (0: S recomputed)
   bool graph = false;
   hipStream_t cap_stream = nullptr;
   isrsgn_fibre_desc desc{};
@@ -523,6 +524,7 @@ int enqueue_grad_stored(isrsgn_fibre* h, PlanEntry* e, const double* P, const do
 // The whole sequence of one call, enqueued on s.
 int enqueue_call(isrsgn_fibre* h, PlanEntry* e, int kind, const double* P, const double* nf, double snr_trx,
                  double* eta, double* pnli, double* tiles, double* snr, double* thr, double* dthr, hipStream_t s) {
+  if (kind == kGrad) h->last_grad_batches = e->store_ok ? (int)e->batches.size() : 0;
   if (kind == kGrad && e->store_ok) return enqueue_grad_stored(h, e, P, nf, snr_trx, snr, thr, dthr, s);
   int m3 = -1;
   int rc = forward(h, e, P, nf, snr_trx, eta, pnli, tiles, snr, thr,
@@ -774,10 +776,11 @@ int isrsgn_stage_times(isrsgn_fibre* h, double* ms, int n) {
 int isrsgn_work_counts(isrsgn_fibre* h, double* out, int n) {
   g_err.clear();
   if (!h || !out || n < 1) return fail(ISRSGN_EINVAL, "handle and output are required");
-  for (int q = 0; q < n && q < 4; ++q) out[q] = 0.0;
+  for (int q = 0; q < n && q < 5; ++q) out[q] = 0.0;
   if (n > 3) out[3] = h->last_variant;
   if (h->plans.empty()) return ISRSGN_OK;
   const PlanEntry* e = h->plans[0].get();
+  if (n > 4) out[4] = h->last_grad_batches;
   unsigned long long nodes = 0;
   hipError_t err = hipMemcpy(&nodes, e->counter.as<char>() + 32, sizeof(nodes), hipMemcpyDeviceToHost);
   if (err != hipSuccess) return hip_fail(err, "work counters");
