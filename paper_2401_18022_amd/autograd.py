@@ -46,9 +46,10 @@ class Throughput(torch.nn.Module):
 
 
 def optimise_launch_power(engine: B.Engine, plan: W.Plan, p_dbm0, steps: int = 50, lr_db: float = 0.05,
-                          lo_dbm: float = -5.0, hi_dbm: float = 5.0, snr_trx_lin: float = 0.0):
+                          lo_dbm: float = -5.0, hi_dbm: float = 5.0, snr_trx_lin: float = 0.0, progress=None):
     """Projected gradient ascent (Adam) of the total throughput over per-channel launch powers in
-    dBm, bounded to [lo_dbm, hi_dbm] as in Sec. IV.  Returns (p_dbm, history of throughput)."""
+    dBm, bounded to [lo_dbm, hi_dbm] as in Sec. IV.  Returns (p_dbm, history of throughput).
+    progress(step, throughput) is called after each step when given."""
     model = Throughput(engine, plan, snr_trx_lin)
     x = torch.tensor(np.asarray(p_dbm0, dtype=np.float64), device="cuda", requires_grad=True)
     opt = torch.optim.Adam([x], lr=lr_db)
@@ -63,4 +64,6 @@ def optimise_launch_power(engine: B.Engine, plan: W.Plan, p_dbm0, steps: int = 5
         with torch.no_grad():
             x.clamp_(lo_dbm, hi_dbm)
         hist.append(total.item())
+        if progress:
+            progress(len(hist), hist[-1])
     return x.detach().cpu().numpy(), hist

@@ -62,6 +62,9 @@ __global__ void k_zero_counter2(unsigned int* c) { *c = 0u; }
 // groups a wave reads at once sit in distinct LDS banks:
 //   key: s1 | s2 << 16 (-1: node off the support), t1, t2, w3a, w3c; w3b = wgt - w3a - w3c.
 constexpr int kMetaStride = 72;  // >= 64 + 64 / MC for MC in {8, 16}
+// Workgroup of the adjoint: four wave64.  (The kernel holds over 168 VGPRs, so 2 waves per
+// SIMD; forcing 3 with six-wave groups spills registers and ran 1.7x slower.)
+__host__ __device__ constexpr int adj_waves(int) { return 4; }
 
 template <int kPrec>
 struct AdjCfg {
@@ -78,7 +81,8 @@ __host__ __device__ inline size_t adjoint_lds_bytes(int nmax, int gs, int M, int
   const int mc = prec == 0 ? 16 : 8;
   const size_t rb = prec == 0 ? 4 : 8;
   return sizeof(double) * (4 * (size_t)nmax + 4 * (size_t)gs + (size_t)nmax + 6 * (size_t)M + 8) +
-         (sizeof(StepLds) + sizeof(Col4)) * (size_t)M + 4 * (size_t)mc * 65 * rb + 4 * 5 * kMetaStride * 4 + 16;
+         (sizeof(StepLds) + sizeof(Col4)) * (size_t)M + adj_waves(prec) * (size_t)mc * 65 * rb +
+         adj_waves(prec) * 5 * kMetaStride * 4 + 16;
 }
 
 // Pass 2 of the FP32 form for one chunk of MC steps at a fixed accuracy tier:
@@ -124,7 +128,8 @@ struct AdjArgs {
 // kStored (FP32 form): S of every node comes from w.s_store, written by the forward tile
 // kernel for the same row batch, instead of a recomputing sweep over the steps.
 template <int kPrec, bool kLinear, bool kStored>
-__global__ void __launch_bounds__(kTileBlock) k_adjoint(AdjArgs A) {
+__global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
+  constexpr int kAdjWaves = adj_waves(kPrec), kAdjBlock = 64 * kAdjWaves;
   using real = typename AdjCfg<kPrec>::real;
   constexpr int MC = AdjCfg<kPrec>::MC;
   constexpr int NG = 64 / MC;  // node groups per wave in the re-mapped phase
@@ -144,12 +149,12 @@ __global__ void __launch_bounds__(kTileBlock) k_adjoint(AdjArgs A) {
   d += 8;
   StepLds* steps = reinterpret_cast<StepLds*>(d);
   Col4* col = reinterpret_cast<Col4*>(steps + M);
-  real* stage = reinterpret_cast<real*>(col + M);  // [4 waves][MC][65] (odd row stride: no bank conflicts)
-  int* mkey = reinterpret_cast<int*>(stage + 4 * MC * 65) + wv * kMetaStride;  // this wave's metadata
-  float2* mt12 = reinterpret_cast<float2*>(reinterpret_cast<int*>(stage + 4 * MC * 65) + 4 * kMetaStride) +
-                 wv * kMetaStride;                                              // (t1, t2)
-  float2* mw3 = mt12 + 4 * kMetaStride;                                          // (w3a, w3c)
-  unsigned int* tile_slot = reinterpret_cast<unsigned int*>(reinterpret_cast<int*>(stage + 4 * MC * 65) + 20 * kMetaStride);
+  real* stage = reinterpret_cast<real*>(col + M);  // [waves][MC][65] (odd row stride: no bank conflicts)
+  int* meta0 = reinterpret_cast<int*>(stage + kAdjWaves * MC * 65);
+  int* mkey = meta0 + wv * kMetaStride;  // this wave's metadata
+  float2* mt12 = reinterpret_cast<float2*>(meta0 + kAdjWaves * kMetaStride) + wv * kMetaStride;  // (t1, t2)
+  float2* mw3 = mt12 + kAdjWaves * kMetaStride;                                                  // (w3a, w3c)
+  unsigned int* tile_slot = reinterpret_cast<unsigned int*>(meta0 + 5 * kAdjWaves * kMetaStride);
   const PlanView& pv = A.pv;
   unsigned int* counter = A.w.counter + 2;
   int cur_b = -1;
@@ -172,8 +177,8 @@ __global__ void __launch_bounds__(kTileBlock) k_adjoint(AdjArgs A) {
       cur_b = b;
     }
     if (kPrec == 0) load_cols<kLinear>(col, A.w.lt32 + (size_t)M * o, n, M, i, k);
-    for (int c = tid; c < n; c += kTileBlock) gGl[c] = 0.0;
-    for (int q = tid; q < 6 * M; q += kTileBlock) tacc[q] = 0.0;
+    for (int c = tid; c < n; c += kAdjBlock) gGl[c] = 0.0;
+    for (int q = tid; q < 6 * M; q += kAdjBlock) tacc[q] = 0.0;
     __syncthreads();
     const TileGeo g = uniform_geo(tile_geo(ch, n, i, k, A.fp.f_ref));
     const double* zm = A.w.zm + (size_t)b * M;
@@ -188,7 +193,7 @@ __global__ void __launch_bounds__(kTileBlock) k_adjoint(AdjArgs A) {
       if (!layout_rows(rw, g, part, GS, GV, A.fp.s_decades)) continue;
       __syncthreads();
       const int64_t nodes = (int64_t)GS * GV;
-      for (int64_t base = 0; base < nodes; base += kTileBlock) {
+      for (int64_t base = 0; base < nodes; base += kAdjBlock) {
         const int64_t q = base + tid;
         Node nd;
         const bool valid = q < nodes && make_node(ch, rw, g, n, k, part, (int)(q / GV), (int)(q % GV), A.fp, &nd);
@@ -382,9 +387,9 @@ __global__ void __launch_bounds__(kTileBlock) k_adjoint(AdjArgs A) {
     gk_acc = block_sum(gk_acc, red);
     if (tid == 0) gGl[k] += gk_acc;
     __syncthreads();
-    for (int c = tid; c < n; c += kTileBlock)
+    for (int c = tid; c < n; c += kAdjBlock)
       if (gGl[c] != 0.0) atomicAdd(&A.w.gG[o + c], gGl[c]);
-    for (int q = tid; q < 6 * M; q += kTileBlock) {
+    for (int q = tid; q < 6 * M; q += kAdjBlock) {
       const int c = hot[q / M], m = q % M;
       const double v = tacc[q];
       if (v != 0.0 && c >= 0 && c < n) atomicAdd(&gL[(size_t)c * M + m], v);
@@ -567,7 +572,8 @@ int adjoint_blocks_per_cu(const FibreParams& fp, int nmax, bool stored) {
     k = fp.profile == 0 ? reinterpret_cast<const void*>(k_adjoint<1, true, false>)
                         : reinterpret_cast<const void*>(k_adjoint<1, false, false>);
   }
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kTileBlock, shm) != hipSuccess || nb < 1) nb = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 64 * adj_waves(fp.precision), shm) != hipSuccess || nb < 1)
+    nb = 1;
   return nb;
 }
 
@@ -589,22 +595,24 @@ hipError_t launch_grad_rows(const PlanView& pv, const double* P, const double* n
 
 hipError_t launch_adjoint_tiles(const PlanView& pv, const FibreParams& fp, const double* P, const Work& w, int nmax,
                                 int grid, unsigned int t_begin, unsigned int t_end, bool stored, hipStream_t s) {
+  if (stored && fp.precision != 0) return hipErrorInvalidValue;  // S is stored by the FP32 form only
   hipLaunchKernelGGL(k_zero_counter2, dim3(1), dim3(1), 0, s, w.counter + 2);
   AdjArgs a{pv, fp, P, w, nmax, t_begin, t_end};
   const size_t shm = adjoint_lds_bytes(nmax, fp.grid_s, fp.n_steps, fp.precision);
+  const void* k;
   if (fp.precision == 0) {
-    if (stored) {
-      if (fp.profile == 0) hipLaunchKernelGGL((k_adjoint<0, true, true>), dim3(grid), dim3(kTileBlock), shm, s, a);
-      else hipLaunchKernelGGL((k_adjoint<0, false, true>), dim3(grid), dim3(kTileBlock), shm, s, a);
-    } else {
-      if (fp.profile == 0) hipLaunchKernelGGL((k_adjoint<0, true, false>), dim3(grid), dim3(kTileBlock), shm, s, a);
-      else hipLaunchKernelGGL((k_adjoint<0, false, false>), dim3(grid), dim3(kTileBlock), shm, s, a);
-    }
+    if (stored) k = fp.profile == 0 ? reinterpret_cast<const void*>(k_adjoint<0, true, true>)
+                                    : reinterpret_cast<const void*>(k_adjoint<0, false, true>);
+    else k = fp.profile == 0 ? reinterpret_cast<const void*>(k_adjoint<0, true, false>)
+                             : reinterpret_cast<const void*>(k_adjoint<0, false, false>);
   } else {
-    if (stored) return hipErrorInvalidValue;  // S is stored by the FP32 form only
-    if (fp.profile == 0) hipLaunchKernelGGL((k_adjoint<1, true, false>), dim3(grid), dim3(kTileBlock), shm, s, a);
-    else hipLaunchKernelGGL((k_adjoint<1, false, false>), dim3(grid), dim3(kTileBlock), shm, s, a);
+    k = fp.profile == 0 ? reinterpret_cast<const void*>(k_adjoint<1, true, false>)
+                        : reinterpret_cast<const void*>(k_adjoint<1, false, false>);
   }
+  if (shm > 65536) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  void* args[] = {&a};
+  hipError_t e = hipLaunchKernel(k, dim3(grid), dim3(64 * adj_waves(fp.precision)), args, shm, s);
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 

@@ -149,6 +149,7 @@ struct isrsgn_fibre {
   DevBuf d_tab_f, d_tab_alpha, d_tab_aeff;
   FibreParams fp{};
   int device = 0, n_cu = 0;
+  size_t lds_max = 65536;  // LDS one workgroup may allocate on this device
   std::vector<std::unique_ptr<PlanEntry>> plans;  // most recent first
   // timing (isrsgn_set_timing): events recorded by the last call and the stage spans between them
   bool timing = false;
@@ -213,9 +214,9 @@ int get_plan(isrsgn_fibre* h, const isrsgn_plan* p, hipStream_t s, PlanEntry** o
     if (n > nmax) nmax = n;
   }
   if (ntiles >= (int64_t)1 << 31) return fail(ISRSGN_EINVAL, "more than 2^31 tiles in one call");
-  if (8 * (4 * (size_t)nmax + 4 * (size_t)h->desc.grid_s + 4) + 32 * (size_t)h->desc.n_steps + 16 > 65536)
-    return fail(ISRSGN_EINVAL, "a plan of %d channels with grid_s %d exceeds the 64 KiB workgroup LDS", nmax,
-                h->desc.grid_s);
+  if (tile_lds(nmax, h->desc.grid_s, h->desc.n_steps) > h->lds_max)
+    return fail(ISRSGN_EINVAL, "a plan of %d channels with grid_s %d and %d steps exceeds the %zu B workgroup LDS",
+                nmax, h->desc.grid_s, h->desc.n_steps, h->lds_max);
   const int total = p->ch_offsets[p->n_batch];
   uint64_t key = 1469598103934665603ull;
   key = fnv1a(p->ch_offsets, sizeof(int) * (p->n_batch + 1), key);
@@ -423,9 +424,9 @@ enum { kEta = 0, kSnr = 1, kGrad = 2 };
 
 int ensure_grad_workspace(isrsgn_fibre* h, PlanEntry* e) {
   const int M = h->desc.n_steps;
-  if (adjoint_lds(e->nmax, h->desc.grid_s, M, h->desc.precision) > 65536)
-    return fail(ISRSGN_EUNSUPPORTED, "the adjoint of a %d-channel plan with grid_s %d and %d steps exceeds 64 KiB LDS",
-                e->nmax, h->desc.grid_s, M);
+  if (adjoint_lds(e->nmax, h->desc.grid_s, M, h->desc.precision) > h->lds_max)
+    return fail(ISRSGN_EUNSUPPORTED, "the adjoint of a %d-channel plan with grid_s %d and %d steps exceeds %zu B LDS",
+                e->nmax, h->desc.grid_s, M, h->lds_max);
   if (e->grad_ready) return ISRSGN_OK;
   const size_t nt = (size_t)e->n_total, nb = (size_t)e->n_batch;
   std::vector<int64_t> soff(nb + 1, 0);
@@ -677,8 +678,11 @@ int isrsgn_setup_fibre(const isrsgn_fibre_desc* d, isrsgn_fibre** out) {
   fp.n_tab = d->n_tab;
   hipError_t err;
   if ((err = hipGetDevice(&h->device)) != hipSuccess) return hip_fail(err, "hipGetDevice");
-  if ((err = hipDeviceGetAttribute(&h->n_cu, hipDeviceAttributeMultiprocessorCount, h->device)) != hipSuccess)
+  int lds_max = 0;
+  if ((err = hipDeviceGetAttribute(&h->n_cu, hipDeviceAttributeMultiprocessorCount, h->device)) != hipSuccess ||
+      (err = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device)) != hipSuccess)
     return hip_fail(err, "device attributes");
+  if (lds_max > 0) h->lds_max = (size_t)lds_max;
   const size_t tb = 8 * (size_t)d->n_tab;
   if (!h->d_tab_f.ensure(tb) || !h->d_tab_alpha.ensure(tb) || !h->d_tab_aeff.ensure(tb))
     return fail(ISRSGN_ENOMEM, "device allocation failed for the fibre tables");

@@ -392,6 +392,8 @@ const char* tile_variant_name(int variant) {
   return variant >= 0 && variant < kTileVariants ? kTileVariantNames[variant] : "?";
 }
 
+size_t tile_lds(int nmax, int gs, int M) { return tile_lds_bytes(nmax, gs, M); }
+
 int tile_blocks_per_cu(const FibreParams& fp, int nmax, int variant) {
   int nb = 0;
   const size_t shm = tile_lds_bytes(nmax, fp.grid_s, fp.n_steps);
@@ -407,9 +409,10 @@ hipError_t launch_tiles(const PlanView& pv, const FibreParams& fp, const double*
   hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, w.counter, reset_nodes ? w.nodes : nullptr);
   TileArgs a{pv, fp, P, w, nmax, t_begin, t_end};
   const size_t shm = tile_lds_bytes(nmax, fp.grid_s, fp.n_steps);
+  const void* k = reinterpret_cast<const void*>(tile_kernel(fp, variant));
+  if (shm > 65536) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   void* args[] = {&a};
-  hipError_t e = hipLaunchKernel(reinterpret_cast<const void*>(tile_kernel(fp, variant)), dim3(grid),
-                                 dim3(kTileBlock), args, shm, s);
+  hipError_t e = hipLaunchKernel(k, dim3(grid), dim3(kTileBlock), args, shm, s);
   if (e != hipSuccess) return e;
   return hipGetLastError();
 }

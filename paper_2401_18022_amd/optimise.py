@@ -64,12 +64,38 @@ def segment_matrix(f_hz: np.ndarray, spacing_hz: float = 100e9):
     return A, counts
 
 
-def gradient_ascent(engine, plan, p_dbm0, steps=50, lr_db=0.05, lo=-5.0, hi=5.0):
+def gradient_ascent(engine, plan, p_dbm0, steps=50, lr_db=0.05, lo=-5.0, hi=5.0, progress=None):
     from .autograd import optimise_launch_power
-    return optimise_launch_power(engine, plan, p_dbm0, steps=steps, lr_db=lr_db, lo_dbm=lo, hi_dbm=hi)
+    return optimise_launch_power(engine, plan, p_dbm0, steps=steps, lr_db=lr_db, lo_dbm=lo, hi_dbm=hi,
+                                 progress=progress)
 
 
-def segment_lbfgsb(engine, plan, x0_dbm=None, lo=-5.0, hi=5.0, pgtol=0.01, maxiter=200):
+def fd_check(plan, fibre, channels, rel_step=10 ** 1e-4 - 1):
+    """dT/dP_k of the FP32 and FP64 adjoints against central differences of the FP64 form at
+    P_k (1 +- rel_step) (a 1e-3 dB change moves T by ~1e-7, below FP32 resolution)."""
+    import torch
+    from . import binding as B
+    e32, e64 = B.Engine(fibre, W.FP32), B.Engine(fibre, W.FP64)
+    P0 = torch.tensor(plan.p_w, dtype=torch.float64, device="cuda")
+    nf = torch.tensor(plan.nf_lin, dtype=torch.float64, device="cuda")
+    g32 = e32.snr_grad(plan, P0, nf)[2].cpu().numpy()
+    g64 = e64.snr_grad(plan, P0, nf)[2].cpu().numpy()
+    rows = []
+    for j, c in enumerate(channels):
+        Pp, Pm = P0.clone(), P0.clone()
+        Pp[c] *= 1 + rel_step
+        Pm[c] *= 1 - rel_step
+        tp = e64.snr(plan, Pp, nf)[1].sum().item()
+        tm = e64.snr(plan, Pm, nf)[1].sum().item()
+        fd = (tp - tm) / (2 * rel_step * plan.p_w[c])
+        rows.append(dict(channel=int(c), fd=fd, adj64=float(g64[c]), adj32=float(g32[c]),
+                         rel64=abs(g64[c] - fd) / abs(fd), rel32=abs(g32[c] - fd) / abs(fd)))
+        print(f"[fd] {j + 1}/{len(channels)} channel {c}: rel err FP64 {rows[-1]['rel64']:.2e} "
+              f"FP32 {rows[-1]['rel32']:.2e}", file=sys.stderr, flush=True)
+    return rows
+
+
+def segment_lbfgsb(engine, plan, x0_dbm=None, lo=-5.0, hi=5.0, pgtol=0.01, maxiter=200, progress=None):
     """Minimise L = -sum log2(1 + SNR_i) (eq. loss) over segment edges in dBm."""
     import torch
     from scipy.optimize import minimize
@@ -79,6 +105,8 @@ def segment_lbfgsb(engine, plan, x0_dbm=None, lo=-5.0, hi=5.0, pgtol=0.01, maxit
     hist = []
 
     def fg(x):
+        if progress:
+            progress(len(hist), hist[-1] if hist else float("nan"))
         p_dbm = A @ x
         P = 1e-3 * np.power(10.0, p_dbm / 10.0)
         snr, thr, g = engine.snr_grad(plan, torch.tensor(P, dtype=torch.float64, device="cuda"), nf)
@@ -104,18 +132,32 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--lbfgsb", action="store_true")
     ap.add_argument("--no-fp64-check", action="store_true", help="skip the FP64-form re-check")
+    ap.add_argument("--fd-check", type=int, default=0, metavar="N",
+                    help="only compare the adjoints with FP64 central differences on N seeded channels")
     args = ap.parse_args(argv)
     wl = W.config_ou(grid_s=args.grid, grid_v=args.grid, n_steps=args.n_steps)
-    eng = B.Engine(wl.fibre, W.FP32)
     out = {"workload": f"O-to-U 589 ch, G={args.grid}, N_M={args.n_steps}, FP32 form"}
+
+    def note(k, thr):
+        print(f"[optimise] evaluation {k}: throughput {thr / 1e12:.4f} Tb/s", file=sys.stderr, flush=True)
+
+    if args.fd_check:
+        t0 = time.perf_counter()
+        rows = fd_check(wl.plan, wl.fibre, W.fd_channels()[:args.fd_check])
+        out.update(method="adjoint vs FP64 central differences (P x 10^(+-1e-4))", channels=rows,
+                   max_rel_fp64=max(r["rel64"] for r in rows), max_rel_fp32=max(r["rel32"] for r in rows),
+                   seconds=time.perf_counter() - t0)
+        print(json.dumps(out), flush=True)
+        return
+    eng = B.Engine(wl.fibre, W.FP32)
     p0 = 10 * np.log10(wl.plan.p_w / 1e-3)
     t0 = time.perf_counter()
     if args.lbfgsb:
-        x, p_dbm, hist, res, counts = segment_lbfgsb(eng, wl.plan)
+        x, p_dbm, hist, res, counts = segment_lbfgsb(eng, wl.plan, progress=note)
         out.update(method="segment L-BFGS-B", edges=int(len(x)), segments_per_band=counts,
                    evaluations=len(hist), converged=bool(res.success), message=str(res.message))
     else:
-        p_dbm, hist = gradient_ascent(eng, wl.plan, p0, steps=args.steps)
+        p_dbm, hist = gradient_ascent(eng, wl.plan, p0, steps=args.steps, progress=note)
         out.update(method="Adam gradient ascent in dBm", steps=args.steps)
     out["seconds"] = time.perf_counter() - t0
     out["throughput_tbps"] = {"initial": hist[0] / 1e12, "final": hist[-1] / 1e12}
