@@ -60,7 +60,8 @@ __global__ void k_zero_counter2(unsigned int* c) { *c = 0u; }
 //
 // Per-node metadata, struct of arrays, group g of MC nodes starting at g (MC + 1) so that the
 // groups a wave reads at once sit in distinct LDS banks:
-//   key: s1 | s2 << 16 (-1: node off the support), t1, t2, w3a, w3c; w3b = wgt - w3a - w3c.
+//   key: s1 | s2 << 16 (-1: node off the support), t1, t2, w3a, w3c (w3b = wgt - w3a - w3c), and
+//   f1, f2: 1 when the node's f1 (f2) segment is the upper of its group's two.
 constexpr int kMetaStride = 72;  // >= 64 + 64 / MC for MC in {8, 16}
 // Workgroup of the adjoint: four wave64.  (The kernel holds over 168 VGPRs, so 2 waves per
 // SIMD; forcing 3 with six-wave groups spills registers and ran 1.7x slower.)
@@ -82,7 +83,7 @@ __host__ __device__ inline size_t adjoint_lds_bytes(int nmax, int gs, int M, int
   const size_t rb = prec == 0 ? 4 : 8;
   return sizeof(double) * (4 * (size_t)nmax + 4 * (size_t)gs + (size_t)nmax + 6 * (size_t)M + 8) +
          (sizeof(StepLds) + sizeof(Col4)) * (size_t)M + adj_waves(prec) * (size_t)mc * 65 * rb +
-         adj_waves(prec) * 5 * kMetaStride * 4 + 16;
+         adj_waves(prec) * 7 * kMetaStride * 4 + 16;
 }
 
 // Pass 2 of the FP32 form for one chunk of MC steps at a fixed accuracy tier:
@@ -154,7 +155,8 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
   int* mkey = meta0 + wv * kMetaStride;  // this wave's metadata
   float2* mt12 = reinterpret_cast<float2*>(meta0 + kAdjWaves * kMetaStride) + wv * kMetaStride;  // (t1, t2)
   float2* mw3 = mt12 + kAdjWaves * kMetaStride;                                                  // (w3a, w3c)
-  unsigned int* tile_slot = reinterpret_cast<unsigned int*>(meta0 + 5 * kAdjWaves * kMetaStride);
+  float2* mff = mw3 + kAdjWaves * kMetaStride;                                                   // (f1, f2)
+  unsigned int* tile_slot = reinterpret_cast<unsigned int*>(meta0 + 7 * kAdjWaves * kMetaStride);
   const PlanView& pv = A.pv;
   unsigned int* counter = A.w.counter + 2;
   int cur_b = -1;
@@ -202,8 +204,8 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
         const double lw = valid ? lam * nd.w : 0.0;
         const int c1 = valid ? nd.c1 : 0, c2 = valid ? nd.c2 : 0;
         const float wgt = kLinear ? 2.0f : 1.0f;
-        int gkey;
-        bool one_run;
+        int gkey, g1lo, g1hi, g2lo, g2hi;
+        bool one_run, two_valued;
         {
           const int jm = lane + lane / MC;
           int key = -1;
@@ -220,18 +222,29 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
           mkey[jm] = key;
           mt12[jm] = valid ? make_float2((float)nd.t1, (float)nd.t2) : make_float2(0.0f, 0.0f);
           mw3[jm] = make_float2(w3a, w3c);
-          // most groups of MC nodes lie in one f1 segment and one f2 segment (one run each);
-          // a wave whose groups all do takes the branch-free re-map below
-          int kmin = key >= 0 ? key : 0x7fffffff, kmax = key;
+          // Most groups of MC nodes lie in one f1 segment and one f2 segment (one run each); nearly
+          // all the others in two of each.  Waves whose groups all do take branch-free re-maps.
+          const int s1v = key >= 0 ? (key & 0xffff) : -1, s2v = key >= 0 ? (key >> 16) : -1;
+          int lo1 = key >= 0 ? s1v : 0x7fffffff, hi1 = s1v, lo2 = key >= 0 ? s2v : 0x7fffffff, hi2 = s2v;
 #pragma unroll
           for (int sh = 1; sh < MC; sh <<= 1) {
-            kmin = min(kmin, __shfl_xor(kmin, sh));
-            kmax = max(kmax, __shfl_xor(kmax, sh));
+            lo1 = min(lo1, __shfl_xor(lo1, sh));
+            hi1 = max(hi1, __shfl_xor(hi1, sh));
+            lo2 = min(lo2, __shfl_xor(lo2, sh));
+            hi2 = max(hi2, __shfl_xor(hi2, sh));
           }
-          gkey = kmax;  // the group's key when it has one run (-1: no node on the support)
-          one_run = kmax < 0 || kmin == kmax;
+          g1lo = lo1;
+          g1hi = hi1;  // -1: no node of the group on the support
+          g2lo = lo2;
+          g2hi = hi2;
+          gkey = hi1 >= 0 ? (hi1 | (hi2 << 16)) : -1;  // the group's key when it has one run
+          one_run = hi1 < 0 || (lo1 == hi1 && lo2 == hi2);
+          two_valued = key < 0 || ((s1v == lo1 || s1v == hi1) && (s2v == lo2 || s2v == hi2));
+          mff[jm] = make_float2(key >= 0 && s1v == hi1 && hi1 != lo1 ? 1.0f : 0.0f,
+                                key >= 0 && s2v == hi2 && hi2 != lo2 ? 1.0f : 0.0f);
         }
         const bool wave_one_run = __all(one_run);
+        const bool wave_two_valued = !wave_one_run && __all(two_valued);
         // pass 1: S
         real sr = 0, si = 0;
         Term32 t32;
@@ -335,6 +348,33 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
               if (!kLinear && gkey >= 0) {
                 flush(gkey & 0xffff, qs, a1h);
                 flush(gkey >> 16, qs, a2h);
+              }
+            } else if (kPrec == 0 && !kLinear && wave_two_valued) {
+              // two runs at most per segment key: the upper run's sums are selected by the
+              // node's 0/1 flag, the lower run's are the rest
+              real b1 = 0, b1h = 0, b2 = 0, b2h = 0;
+#pragma unroll 4
+              for (int it = 0; it < MC; ++it) {
+                const real qv = qrow[it];
+                const float2 w3 = mw3[jb + it];
+                const float2 tt = mt12[jb + it];
+                const float2 ff = mff[jb + it];
+                qs += qv;
+                x3a += qv * (real)w3.x;
+                x3c += qv * (real)w3.y;
+                const real u1 = qv * (real)tt.x, u2 = qv * (real)tt.y;
+                a1h += u1;
+                a2h += u2;
+                b1 += qv * (real)ff.x;
+                b1h += u1 * (real)ff.x;
+                b2 += qv * (real)ff.y;
+                b2h += u2 * (real)ff.y;
+              }
+              if (g1hi >= 0) {
+                flush(g1lo, qs - b1, a1h - b1h);
+                if (g1hi != g1lo) flush(g1hi, b1, b1h);
+                flush(g2lo, qs - b2, a2h - b2h);
+                if (g2hi != g2lo) flush(g2hi, b2, b2h);
               }
             } else {
 #pragma unroll 4
