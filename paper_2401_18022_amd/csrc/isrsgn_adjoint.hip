@@ -126,8 +126,8 @@ struct AdjArgs {
   unsigned int t_begin, t_end;  // tiles [t_begin, t_end) of the concatenated tile list
 };
 
-// kStored (FP32 form): S of every node comes from w.s_store, written by the forward tile
-// kernel for the same row batch, instead of a recomputing sweep over the steps.
+// kStored: S of every node comes from w.s_store, written by the forward tile kernel for the
+// same row batch, instead of a recomputing sweep over the steps.
 template <int kPrec, bool kLinear, bool kStored>
 __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
   constexpr int kAdjWaves = adj_waves(kPrec), kAdjBlock = 64 * kAdjWaves;
@@ -257,9 +257,17 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
         const int tier = wave_tier(tsmall, tlarge);
         if (valid) {
           if (kStored) {
-            const float2 sv = A.w.s_store[((int64_t)(t - A.t_begin) * 3 + part) * nodes + q];
-            sr = sv.x;
-            si = sv.y;
+            const int64_t slot = ((int64_t)(t - A.t_begin) * 3 + part) * nodes + q;
+            if constexpr (kPrec == 0) {
+              const float2 sv = static_cast<const float2*>(A.w.s_store)[slot];
+              sr = sv.x;
+              si = sv.y;
+            } else {
+              const double2 sv = static_cast<const double2*>(A.w.s_store)[slot];
+              sr = sv.x;
+              si = sv.y;
+            }
+            if (kPrec == 1) t64 = term64_setup(nd, i);
           } else if (kPrec == 0) {
             const Tab32 tab = make_tab32(A.w.lt32 + (size_t)M * o, n, M);
             float a32, b32;
@@ -609,8 +617,10 @@ int adjoint_blocks_per_cu(const FibreParams& fp, int nmax, bool stored) {
     else k = fp.profile == 0 ? reinterpret_cast<const void*>(k_adjoint<0, true, false>)
                              : reinterpret_cast<const void*>(k_adjoint<0, false, false>);
   } else {
-    k = fp.profile == 0 ? reinterpret_cast<const void*>(k_adjoint<1, true, false>)
-                        : reinterpret_cast<const void*>(k_adjoint<1, false, false>);
+    if (stored) k = fp.profile == 0 ? reinterpret_cast<const void*>(k_adjoint<1, true, true>)
+                                    : reinterpret_cast<const void*>(k_adjoint<1, false, true>);
+    else k = fp.profile == 0 ? reinterpret_cast<const void*>(k_adjoint<1, true, false>)
+                             : reinterpret_cast<const void*>(k_adjoint<1, false, false>);
   }
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 64 * adj_waves(fp.precision), shm) != hipSuccess || nb < 1)
     nb = 1;
@@ -635,7 +645,6 @@ hipError_t launch_grad_rows(const PlanView& pv, const double* P, const double* n
 
 hipError_t launch_adjoint_tiles(const PlanView& pv, const FibreParams& fp, const double* P, const Work& w, int nmax,
                                 int grid, unsigned int t_begin, unsigned int t_end, bool stored, hipStream_t s) {
-  if (stored && fp.precision != 0) return hipErrorInvalidValue;  // S is stored by the FP32 form only
   hipLaunchKernelGGL(k_zero_counter2, dim3(1), dim3(1), 0, s, w.counter + 2);
   AdjArgs a{pv, fp, P, w, nmax, t_begin, t_end};
   const size_t shm = adjoint_lds_bytes(nmax, fp.grid_s, fp.n_steps, fp.precision);
@@ -646,8 +655,10 @@ hipError_t launch_adjoint_tiles(const PlanView& pv, const FibreParams& fp, const
     else k = fp.profile == 0 ? reinterpret_cast<const void*>(k_adjoint<0, true, false>)
                              : reinterpret_cast<const void*>(k_adjoint<0, false, false>);
   } else {
-    k = fp.profile == 0 ? reinterpret_cast<const void*>(k_adjoint<1, true, false>)
-                        : reinterpret_cast<const void*>(k_adjoint<1, false, false>);
+    if (stored) k = fp.profile == 0 ? reinterpret_cast<const void*>(k_adjoint<1, true, true>)
+                                    : reinterpret_cast<const void*>(k_adjoint<1, false, true>);
+    else k = fp.profile == 0 ? reinterpret_cast<const void*>(k_adjoint<1, true, false>)
+                             : reinterpret_cast<const void*>(k_adjoint<1, false, false>);
   }
   if (shm > 65536) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   void* args[] = {&a};

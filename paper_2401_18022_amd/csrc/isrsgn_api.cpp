@@ -441,17 +441,18 @@ int ensure_grad_workspace(isrsgn_fibre* h, PlanEntry* e) {
   if (!ok) return fail(ISRSGN_ENOMEM, "device allocation failed for the adjoint workspace");
   hipError_t err = hipMemcpy(e->state_off.p, soff.data(), 8 * (nb + 1), hipMemcpyHostToDevice);
   if (err != hipSuccess) return hip_fail(err, "state offsets");
-  // FP32 form: the forward pass keeps S of every node for the adjoint, one batch of complete
-  // COI rows at a time (a row's SNR, and so its upstream weight, needs only that row).  The
-  // store is bounded by ISRSGN_STORE_MB (default 16384 MiB; 0 disables it); when a row does not
-  // fit or the allocation fails, the adjoint recomputes S instead.
+  // The forward pass keeps S of every node for the adjoint (8 B per node in the FP32 form, 16 B
+  // in the FP64 form), one batch of complete COI rows at a time (a row's SNR, and so its
+  // upstream weight, needs only that row).  The store is bounded by ISRSGN_STORE_MB (default
+  // 16384 MiB; 0 disables it); when a row does not fit or the allocation fails, the adjoint
+  // recomputes S instead.
   e->batches.clear();
   e->store_ok = false;
   const char* env = std::getenv("ISRSGN_STORE_MB");
   const double store_mb = env && *env ? std::atof(env) : 16384.0;
-  const int64_t per_tile = (int64_t)3 * h->desc.grid_s * h->desc.grid_v * (int64_t)sizeof(float2);
-  const int64_t max_tiles = h->desc.precision == ISRSGN_FP32 && store_mb > 0
-                                ? (int64_t)(store_mb * 1048576.0 / (double)per_tile) : 0;
+  const int64_t per_tile = (int64_t)3 * h->desc.grid_s * h->desc.grid_v *
+                           (int64_t)(h->desc.precision == ISRSGN_FP32 ? sizeof(float2) : sizeof(double2));
+  const int64_t max_tiles = store_mb > 0 ? (int64_t)(store_mb * 1048576.0 / (double)per_tile) : 0;
   bool fits = max_tiles > 0;
   for (size_t b = 0; b < nb && fits; ++b) fits = e->off[b + 1] - e->off[b] <= max_tiles;
   if (fits) {
@@ -490,7 +491,7 @@ int enqueue_grad_stored(isrsgn_fibre* h, PlanEntry* e, const double* P, const do
   int variant = 0, mk = -1;
   const int rc = prologue(h, e, P, w, h->desc.profile == ISRSGN_PROFILE_ODE, s, &variant, &mk);
   if (rc) return rc;
-  w.s_store = e->s_store.as<float2>();
+  w.s_store = e->s_store.p;
   hipError_t err = launch_grad_init(pv, h->fp, w, s);
   if (err != hipSuccess) return hip_fail(err, "adjoint");
   const int adj_per_cu = adjoint_blocks_per_cu(h->fp, e->nmax, true);

@@ -52,9 +52,10 @@ struct Work {
   double* snr;      // [n_total]
   unsigned int* counter;  // work counter of the persistent tile kernels
   unsigned long long* nodes;  // nodes evaluated by the last forward tile launch
-  // FP32 form with a gradient: S of every node of the current row batch, written by the
-  // forward tile kernel and read by the adjoint ([tile - t_begin][part][node]), or null
-  float2* s_store;
+  // gradient: S of every node of the current row batch, written by the forward tile kernel
+  // and read by the adjoint ([tile - t_begin][part][node]; float2 in the FP32 form, double2
+  // in the FP64 form), or null
+  void* s_store;
   // adjoint
   double* states;   // ODE states, plan b at sstate_off[b]: [(M*2*ode_sub + 1) * N_b]
   const int64_t* state_off;
@@ -87,7 +88,7 @@ hipError_t launch_copy_profile(const PlanView& pv, const FibreParams& fp, const 
                                double* dz, double* ell, double* ellL, hipStream_t s);
 // The gradient in pieces (row batches): clear dT/d ell and dT/dG; upstream weights of the
 // channels [g_begin, g_end); the adjoint of tiles [t_begin, t_end) (stored: S comes from
-// w.s_store instead of a recomputing sweep, FP32 form only); profile adjoint and assembly.
+// w.s_store instead of a recomputing sweep); profile adjoint and assembly.
 hipError_t launch_grad_init(const PlanView& pv, const FibreParams& fp, const Work& w, hipStream_t s);
 hipError_t launch_grad_rows(const PlanView& pv, const double* P, const double* nf, double snr_trx, const Work& w,
                             int g_begin, int g_end, hipStream_t s);

@@ -241,7 +241,8 @@ k_tiles(TileArgs A) {
           else if (tier == kTierLarge) accumulate32<kLinear, kTierLarge, kUnroll>(tq, steps, col, tab, n, M, &sr, &si);
           else accumulate32<kLinear, kTierMixed, kUnroll>(tq, steps, col, tab, n, M, &sr, &si);
           s2v = (double)sr * sr + (double)si * si;
-          if (A.w.s_store) A.w.s_store[((int64_t)(t - A.t_begin) * 3 + part) * nodes + q] = make_float2(sr, si);
+          if (A.w.s_store)
+            static_cast<float2*>(A.w.s_store)[((int64_t)(t - A.t_begin) * 3 + part) * nodes + q] = make_float2(sr, si);
         } else {
           const Term64 tq = term64_setup(nd, i);
           const double* tab = A.w.ell64 + (size_t)M * o;
@@ -253,6 +254,8 @@ k_tiles(TileArgs A) {
             si += a.y;
           }
           s2v = sr * sr + si * si;
+          if (A.w.s_store)
+            static_cast<double2*>(A.w.s_store)[((int64_t)(t - A.t_begin) * 3 + part) * nodes + q] = make_double2(sr, si);
         }
         acc += nd.w * nd.gprod * s2v;
         ++evaluated;

@@ -110,32 +110,36 @@ def test_batch_workload_sample_matches_oracle():
         np.testing.assert_allclose(snr.cpu().numpy()[lo + np.array(coi)], r["snr"], rtol=2e-6)
 
 
-def test_row_batched_gradient_matches_recompute():
-    """FP32 gradient with S kept per batch of COI rows -- store disabled (S recomputed by the
+@pytest.mark.parametrize("prec", [W.FP32, W.FP64])
+def test_row_batched_gradient_matches_recompute(prec):
+    """Gradient with S kept per batch of COI rows -- store disabled (S recomputed by the
     adjoint), a 5 MiB store (a dozen row batches) and the default store -- gives the same
-    gradient (to the rounding of FP64 atomics), and the same SNR and throughput as the
-    SNR-only call, bit for bit."""
+    gradient (to the rounding of FP64 atomics and of the FP32 run sums), and the same SNR and
+    throughput as the SNR-only call, bit for bit."""
     t = torch()
     wl = W.config_cl(grid_s=16, grid_v=16, n_steps=24)
     P = t.tensor(wl.plan.p_w, dtype=t.float64, device="cuda")
     nf = t.tensor(wl.plan.nf_lin, dtype=t.float64, device="cuda")
-    res, nodes = {}, {}
+    res, nodes, batches = {}, {}, {}
     for mb in ("0", "5", "16384"):
         os.environ["ISRSGN_STORE_MB"] = mb
         try:
-            eng = B.Engine(wl.fibre, W.FP32)
+            eng = B.Engine(wl.fibre, prec)
             res[mb] = eng.snr_grad(wl.plan, P, nf)
             t.cuda.synchronize()
-            nodes[mb] = eng.work_counts()["nodes"]
+            wc = eng.work_counts()
+            nodes[mb], batches[mb] = wc["nodes"], wc["grad_batches"]
         finally:
             del os.environ["ISRSGN_STORE_MB"]
+    assert batches["0"] == 0 and batches["5"] > 4 and batches["16384"] == 1, batches
     snr1, thr1 = eng.snr(wl.plan, P, nf)
     t.cuda.synchronize()
     ref = res["0"]
     scale = ref[2].abs().max().item()
+    tol = 1e-6 if prec == W.FP32 else 1e-12
     for mb in ("5", "16384"):
         snr, thr, g = res[mb]
         assert t.equal(snr, ref[0]) and t.equal(thr, ref[1]), mb
-        assert (g - ref[2]).abs().max().item() <= 1e-6 * scale, mb
+        assert (g - ref[2]).abs().max().item() <= tol * scale, mb
         assert nodes[mb] == nodes["0"], mb
     assert t.equal(snr1, ref[0]) and t.equal(thr1, ref[1])
