@@ -30,7 +30,9 @@
 //     P2 profile = RK4 on the Raman ODEs (triangular gain with cut-off,
 //     photon-number ratio, A_eff scaling), ln rho interpolated linearly in f
 //     between channel centres;
-//   * NLI power = R_i G(f_i); ASE = NF h f G_amp R with G_amp = 1/rho(L, f).
+//   * NLI power = R_i G(f_i); ASE = NF h f G_amp R with G_amp = 1/rho(L, f);
+//   * n identical spans: each amplifier restores the launch power, so every span has the same
+//     power profile and adds the same ASE; span k's field carries the phase phi (k-1) L.
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -107,6 +109,7 @@ typedef struct {
   int n_threads;
   int unfold;  // 1: evaluate both sides of each fold explicitly (symmetry check)
   int mode;    // 0: model integrand; 1: unit integrand; 2: unit integrand on the channel support
+  int n_spans;  // identical spans (App. A, eq. gain: sum over spans k with offsets (k-1) L)
 } orc_problem;
 
 }  // extern "C"
@@ -418,15 +421,21 @@ T psi(const Model& md, const Profile<T>& pr, const std::vector<T>& G, int i, dou
   T gprod = G[c1] * G[c2] * G[c3];
   double phi = phase_mismatch(x, y, fi - pb.f_ref_hz, pb.beta2, pb.beta3, pb.beta4);
   T sre(0.0), sim(0.0);
-  for (int m = 0; m < (int)md.st.zm.size(); ++m) {
-    // eq. (pk): p = sqrt(rho(f1) rho(f2) rho(f1+f2-f) / rho(f))
-    T p = Exp((pr.lnrho(m, fi + x) + pr.lnrho(m, fi + y) + pr.lnrho(m, fi + x + y) - pr.lnrho(m, fi)) * 0.5);
-    double dz = md.st.dz[m], zm = md.st.zm[m];
-    double u = phi * dz / 2;
-    double sinc = u == 0.0 ? 1.0 : std::sin(u) / u;
-    T amp = p * (dz * sinc);
-    sre += amp * std::cos(phi * zm);
-    sim += amp * std::sin(phi * zm);
+  // eq. (psi_fin): sum over the n identical spans (offset (k-1) L, the same power profile in
+  // each: the amplifiers restore the launch power) and over the steps of a span
+  const int n_spans = pb.n_spans > 0 ? pb.n_spans : 1;
+  for (int k = 0; k < n_spans; ++k) {
+    const double off = k * pb.span_m;
+    for (int m = 0; m < (int)md.st.zm.size(); ++m) {
+      // eq. (pk): p = sqrt(rho(f1) rho(f2) rho(f1+f2-f) / rho(f))
+      T p = Exp((pr.lnrho(m, fi + x) + pr.lnrho(m, fi + y) + pr.lnrho(m, fi + x + y) - pr.lnrho(m, fi)) * 0.5);
+      double dz = md.st.dz[m], zm = md.st.zm[m];
+      double u = phi * dz / 2;
+      double sinc = u == 0.0 ? 1.0 : std::sin(u) / u;
+      T amp = p * (dz * sinc);
+      sre += amp * std::cos(phi * (off + zm));
+      sim += amp * std::sin(phi * (off + zm));
+    }
   }
   return gprod * (sre * sre + sim * sim);
 }
@@ -578,8 +587,9 @@ int forward_impl(const orc_problem* pb, int n_coi, const int* coi, double* tiles
     T pn = row * ((16.0 / 27.0) * ch.gamma[i] * ch.gamma[i] * ch.R[i]);
     T pi = P[i];
     T et = Val(pi) > 0 ? pn / (pi * pi * pi) : T(std::numeric_limits<double>::quiet_NaN());
-    // ASE: NF h f G_amp R with the amplifier restoring the launch power, G_amp = 1/rho(L, f_i)
-    T pase = Exp(-pr.lnrho(-1, ch.f[i])) * (ch.nf[i] * kH * ch.f[i] * ch.R[i]);
+    // ASE: NF h f G_amp R with the amplifier restoring the launch power, G_amp = 1/rho(L, f_i),
+    // one amplifier per span
+    T pase = Exp(-pr.lnrho(-1, ch.f[i])) * (ch.nf[i] * kH * ch.f[i] * ch.R[i] * (pb->n_spans > 0 ? pb->n_spans : 1));
     T sn(0.0);
     if (Val(pi) > 0) {
       sn = pi / (pn + pase);

@@ -32,7 +32,7 @@ class Problem(C.Structure):
         ("s_decades", C.c_double), ("ode_sub", C.c_int),
         ("n_ch", C.c_int), ("f_hz", _dp), ("rs_hz", _dp), ("p_w", _dp), ("nf_lin", _dp),
         ("snr_trx", C.c_double), ("dp", _dp), ("n_threads", C.c_int), ("unfold", C.c_int),
-        ("mode", C.c_int),
+        ("mode", C.c_int), ("n_spans", C.c_int),
     ]
 
 
@@ -116,6 +116,7 @@ class Oracle:
         pb.dp = None
         pb.n_threads = int(n_threads or min(16, os.cpu_count() or 1))
         pb.unfold, pb.mode = unfold, mode
+        pb.n_spans = int(getattr(fibre, "n_spans", 1))
         self.pb = pb
         self.n = len(f)
 

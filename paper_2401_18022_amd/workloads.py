@@ -63,6 +63,7 @@ class Fibre:
     s_decades: float = 14.0
     ode_sub: int = 2
     precision: int = FP32
+    n_spans: int = 1                   # identical spans, each followed by an amplifier
 
     def replace(self, **kw) -> "Fibre":
         return dataclasses.replace(self, **kw)

@@ -452,3 +452,43 @@ def test_dual_gradient_matches_central_differences(profile):
     assert r["dthr"] == pytest.approx((tp["thr"] - tm["thr"]) / (2 * h), rel=1e-6)
     np.testing.assert_allclose(r["dsnr"], (tp["snr"] - tm["snr"]) / (2 * h), rtol=1e-6)
     np.testing.assert_allclose(r["dtiles"], (tp["tiles"] - tm["tiles"]) / (2 * h), rtol=1e-5, atol=1e-9 * np.abs(r["dtiles"]).max())
+
+
+# ----------------------------------------------------------------------------- several spans
+def test_spans_sum_to_the_phased_array_factor():
+    """n identical spans (App. A, eq. gain summed over spans with offsets (k-1) L): the oracle
+    sums the spans' fields explicitly; |sum_k e^(j phi (k-1) L)|^2 = sin^2(n phi L/2) /
+    sin^2(phi L/2) turns it into the single-span integrand times the phased-array factor."""
+    wl = W.random_small(6, seed=21, grid_s=8, grid_v=8, n_steps=20)
+    b2, b3, b4 = O.betas(wl.fibre)
+    rng = np.random.default_rng(22)
+    plan = wl.plan
+    i = 2
+    fi = plan.f_hz[i]
+    band = (plan.f_hz[0] - plan.rs_hz[0] / 2, plan.f_hz[-1] + plan.rs_hz[-1] / 2)
+    x = rng.uniform(band[0], band[1], 40) - fi
+    y = rng.uniform(band[0], band[1], 40) - fi
+    one = O.Oracle(wl.fibre, plan).psi(i, x, y)
+    for n in (2, 3, 7):
+        many = O.Oracle(wl.fibre.replace(n_spans=n), plan).psi(i, x, y)
+        phi = np.array([O.phi(a, b, fi - wl.fibre.f_ref_hz, b2, b3, b4) for a, b in zip(x, y)])
+        h = phi * wl.fibre.span_m / 2
+        af = np.where(np.abs(np.sin(h)) > 1e-12, np.sin(n * h) ** 2 / np.maximum(np.sin(h) ** 2, 1e-300), n * n)
+        keep = one > 0
+        assert keep.sum() > 10
+        np.testing.assert_allclose(many[keep], one[keep] * af[keep], rtol=1e-9)
+
+
+def test_spans_without_dispersion_add_coherently_and_ase_adds_per_span():
+    """With no dispersion (phi = 0) the spans' fields add in phase: NLI grows as n^2; every span's
+    amplifier adds the same ASE: n times the single-span ASE."""
+    wl = W.config_tiny(grid_s=12, grid_v=12, n_steps=16)
+    fb = wl.fibre.replace(beta2=0.0, beta3=0.0, beta4=0.0, disp_from_d=0)
+    r1 = O.Oracle(fb, wl.plan).forward()
+    r3 = O.Oracle(fb.replace(n_spans=3), wl.plan).forward()
+    np.testing.assert_allclose(r3["tiles"], 9.0 * r1["tiles"], rtol=1e-12)
+    # ASE only: SNR at a power so low that NLI is negligible
+    low = wl.plan.with_power(wl.plan.p_w * 1e-6)
+    s1 = O.Oracle(wl.fibre, low).forward()["snr"]
+    s4 = O.Oracle(wl.fibre.replace(n_spans=4), low).forward()["snr"]
+    np.testing.assert_allclose(s4, s1 / 4.0, rtol=1e-9)
