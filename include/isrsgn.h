@@ -82,6 +82,10 @@ typedef struct {
   double s_decades;         /* depth of the ln|xy| window below sup|xy|, > 0 (14 is ample) */
   int ode_sub;              /* ODE: RK4 sub-steps per half distance step, 1..64 */
   int precision;            /* ISRSGN_FP32 (FP32 integrand, FP64 phase and sums) or ISRSGN_FP64 */
+  int n_spans;              /* identical spans, each followed by an amplifier restoring the launch
+                             * power (App. A, eq. gain summed over spans), 1..100000: every node's
+                             * |S|^2 carries the phased-array factor sin^2(n phi L/2)/sin^2(phi L/2)
+                             * and the ASE is n times one span's */
 } isrsgn_fibre_desc;
 
 /* One or more channel plans, concatenated CSR-style (host memory).

@@ -39,7 +39,7 @@ class FibreDesc(C.Structure):
         ("cr_per_w_m_hz", C.c_double), ("aeff_ref_m2", C.c_double), ("raman_cutoff_hz", C.c_double),
         ("profile", C.c_int), ("photon_ratio", C.c_int), ("n_steps", C.c_int),
         ("grid_s", C.c_int), ("grid_v", C.c_int), ("s_decades", C.c_double), ("ode_sub", C.c_int),
-        ("precision", C.c_int),
+        ("precision", C.c_int), ("n_spans", C.c_int),
     ]
 
 
@@ -105,6 +105,7 @@ def make_desc(fibre: W.Fibre, precision: Optional[int] = None):
     d.n_steps, d.grid_s, d.grid_v = fibre.n_steps, fibre.grid_s, fibre.grid_v
     d.s_decades, d.ode_sub = fibre.s_decades, fibre.ode_sub
     d.precision = fibre.precision if precision is None else precision
+    d.n_spans = fibre.n_spans
     return d, keep
 
 

@@ -13,13 +13,13 @@ namespace {
 // dT/dN_i * 16/27 gamma_i^2 R_i; gP_i starts as the direct dT/dP_i; gLL_i = dT/d ln rho(L, f_i)
 // through the ASE term.
 __global__ void k_grad_prep(PlanView pv, const double* __restrict__ P, const double* __restrict__ nf, double snr_trx,
-                            Work w, int g_begin, int g_end) {
+                            Work w, int g_begin, int g_end, int n_spans) {
   const int g = g_begin + blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= g_end) return;
   const double p = P[g], R = pv.R[g], f = pv.f[g], gm = pv.gamma[g];
   double lamN = 0.0, direct = 0.0, pase = 0.0;
   if (p > 0.0) {
-    pase = nf[g] * kH * f * R * exp(-w.ellL[g]);
+    pase = nf[g] * kH * f * R * exp(-w.ellL[g]) * n_spans;  // one amplifier per span
     const double N = w.pnli[g] + pase, s0 = p / N;
     double snr = s0, dsnr = 1.0;
     if (snr_trx > 0.0) {
@@ -635,11 +635,11 @@ hipError_t launch_grad_init(const PlanView& pv, const FibreParams& fp, const Wor
   return hipGetLastError();
 }
 
-hipError_t launch_grad_rows(const PlanView& pv, const double* P, const double* nf, double snr_trx, const Work& w,
-                            int g_begin, int g_end, hipStream_t s) {
+hipError_t launch_grad_rows(const PlanView& pv, const FibreParams& fp, const double* P, const double* nf,
+                            double snr_trx, const Work& w, int g_begin, int g_end, hipStream_t s) {
   if (g_end <= g_begin) return hipSuccess;
   hipLaunchKernelGGL(k_grad_prep, dim3((unsigned)((g_end - g_begin + 255) / 256)), dim3(256), 0, s, pv, P, nf,
-                     snr_trx, w, g_begin, g_end);
+                     snr_trx, w, g_begin, g_end, fp.n_spans);
   return hipGetLastError();
 }
 

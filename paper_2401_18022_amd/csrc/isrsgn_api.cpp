@@ -185,6 +185,7 @@ int validate_desc(const isrsgn_fibre_desc* d) {
   if (d->grid_v < 2 || d->grid_v > 65536) return fail(ISRSGN_EINVAL, "grid_v must be in 2..65536");
   if (!(d->s_decades > 0) || d->s_decades > 40) return fail(ISRSGN_EINVAL, "s_decades must be in (0, 40]");
   if (d->ode_sub < 1 || d->ode_sub > 64) return fail(ISRSGN_EINVAL, "ode_sub must be in 1..64");
+  if (d->n_spans < 1 || d->n_spans > 100000) return fail(ISRSGN_EINVAL, "n_spans must be in 1..100000");
   if (!(d->cr_per_w_m_hz >= 0) || !(d->aeff_ref_m2 > 0)) return fail(ISRSGN_EINVAL, "need cr >= 0 and aeff_ref > 0");
   if (!(d->n2_m2_per_w >= 0) || !(d->gamma_const_per_w_m >= 0)) return fail(ISRSGN_EINVAL, "need n2, gamma >= 0");
   const double vals[] = {d->beta2, d->beta3, d->beta4, d->d_s_per_m2, d->s_s_per_m3, d->sdot_s_per_m4,
@@ -504,8 +505,8 @@ int enqueue_grad_stored(isrsgn_fibre* h, PlanEntry* e, const double* P, const do
     first = false;
     const int ma = mark(h, s);
     add_span(h, 1, mk, ma);
-    err = launch_reduce_rows(pv, P, nf, snr_trx, w, nullptr, nullptr, snr, bt.g0, bt.g1, s);
-    if (err == hipSuccess) err = launch_grad_rows(pv, P, nf, snr_trx, w, bt.g0, bt.g1, s);
+    err = launch_reduce_rows(pv, h->fp, P, nf, snr_trx, w, nullptr, nullptr, snr, bt.g0, bt.g1, s);
+    if (err == hipSuccess) err = launch_grad_rows(pv, h->fp, P, nf, snr_trx, w, bt.g0, bt.g1, s);
     if (err != hipSuccess) return hip_fail(err, "reduction");
     const int mb = mark(h, s);
     add_span(h, 2, ma, mb);
@@ -538,7 +539,7 @@ int enqueue_call(isrsgn_fibre* h, PlanEntry* e, int kind, const double* P, const
   const Work w = e->work();
   const PlanView pv = e->view();
   hipError_t err = launch_grad_init(pv, h->fp, w, s);
-  if (err == hipSuccess) err = launch_grad_rows(pv, P, nf, snr_trx, w, 0, pv.n_total, s);
+  if (err == hipSuccess) err = launch_grad_rows(pv, h->fp, P, nf, snr_trx, w, 0, pv.n_total, s);
   if (err == hipSuccess)
     err = launch_adjoint_tiles(pv, h->fp, P, w, e->nmax, (int)(grid < 1 ? 1 : grid), 0u, (unsigned int)e->n_tiles,
                                false, s);
@@ -675,6 +676,7 @@ int isrsgn_setup_fibre(const isrsgn_fibre_desc* d, isrsgn_fibre** out) {
   fp.grid_v = d->grid_v;
   fp.ode_sub = d->ode_sub;
   fp.precision = d->precision;
+  fp.n_spans = d->n_spans;
   fp.s_decades = d->s_decades;
   fp.n_tab = d->n_tab;
   hipError_t err;

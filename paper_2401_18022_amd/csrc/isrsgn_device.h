@@ -323,6 +323,16 @@ struct Node {
   double t1, t2, t3;
 };
 
+// n identical spans: the spans' fields differ by the phase phi (k-1) L, so |S|^2 gains the
+// phased-array factor |sum_k e^(j phi (k-1) L)|^2 = sin^2(n phi L/2) / sin^2(phi L/2) (App. A).
+// x = phi L / (2 pi) in revolutions; the factor has period 1 in x and tends to n^2 at integers.
+__device__ inline double span_array_factor(double x, int n) {
+  const double r = x - rint(x);
+  if (fabs(r) < 1e-12) return (double)n * n;
+  const double q = sinpi(n * r) / sinpi(r);
+  return q * q;
+}
+
 __device__ inline bool make_node(const ChanLds& ch, const RowLds& rw, const TileGeo& g, int n, int k, int part,
                                  int a, int bcol, const FibreParams& fp, Node* nd) {
   const double dv = rw.dv[a];
@@ -340,6 +350,7 @@ __device__ inline bool make_node(const ChanLds& ch, const RowLds& rw, const Tile
   nd->c2 = c2;
   nd->gprod = ch.psd[c1] * ch.psd[c2] * g.gk;
   nd->phr = phase_mismatch(x, y, g.wi, fp.b2, fp.b3, fp.b4) * (0.5 / kPi);
+  if (fp.n_spans > 1) nd->w *= span_array_factor(nd->phr * fp.span, fp.n_spans);
   segment(ch, n, c1, g.fi + x, &nd->s1, &nd->t1);
   segment(ch, n, c2, g.fi + y, &nd->s2, &nd->t2);
   segment(ch, n, k, g.fi + x + y, &nd->s3, &nd->t3);

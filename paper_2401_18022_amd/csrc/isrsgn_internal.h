@@ -31,6 +31,7 @@ struct FibreParams {
   double span, f_ref, b2, b3, b4;
   double n2, gamma_const, cr, aeff_ref, cutoff;
   int profile, photon_ratio, n_steps, grid_s, grid_v, ode_sub, precision;
+  int n_spans;  // identical spans: phased-array factor per node, n-fold ASE
   double s_decades;
   int n_tab;
   const double* tab_f;      // device copies of the tables
@@ -80,9 +81,9 @@ hipError_t launch_reduce(const PlanView& pv, const FibreParams& fp, const double
                          double snr_trx, const Work& w, double* eta, double* pnli_out, double* snr_out,
                          double* thr_out, hipStream_t s);
 // P_NLI, eta and SNR of the global channels [g_begin, g_end) (their tile rows must be complete)
-hipError_t launch_reduce_rows(const PlanView& pv, const double* P, const double* nf, double snr_trx, const Work& w,
-                              double* eta, double* pnli_out, double* snr_out, int g_begin, int g_end,
-                              hipStream_t s);
+hipError_t launch_reduce_rows(const PlanView& pv, const FibreParams& fp, const double* P, const double* nf,
+                              double snr_trx, const Work& w, double* eta, double* pnli_out, double* snr_out,
+                              int g_begin, int g_end, hipStream_t s);
 hipError_t launch_throughput(const PlanView& pv, const double* P, const Work& w, double* thr_out, hipStream_t s);
 hipError_t launch_copy_profile(const PlanView& pv, const FibreParams& fp, const Work& w, double* zm,
                                double* dz, double* ell, double* ellL, hipStream_t s);
@@ -90,8 +91,8 @@ hipError_t launch_copy_profile(const PlanView& pv, const FibreParams& fp, const 
 // channels [g_begin, g_end); the adjoint of tiles [t_begin, t_end) (stored: S comes from
 // w.s_store instead of a recomputing sweep); profile adjoint and assembly.
 hipError_t launch_grad_init(const PlanView& pv, const FibreParams& fp, const Work& w, hipStream_t s);
-hipError_t launch_grad_rows(const PlanView& pv, const double* P, const double* nf, double snr_trx, const Work& w,
-                            int g_begin, int g_end, hipStream_t s);
+hipError_t launch_grad_rows(const PlanView& pv, const FibreParams& fp, const double* P, const double* nf,
+                            double snr_trx, const Work& w, int g_begin, int g_end, hipStream_t s);
 hipError_t launch_adjoint_tiles(const PlanView& pv, const FibreParams& fp, const double* P, const Work& w, int nmax,
                                 int grid, unsigned int t_begin, unsigned int t_end, bool stored, hipStream_t s);
 hipError_t launch_grad_finish(const PlanView& pv, const FibreParams& fp, const double* P, const Work& w,

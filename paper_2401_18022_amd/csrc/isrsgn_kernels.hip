@@ -281,7 +281,8 @@ __global__ void k_zero_counter(unsigned int* c, unsigned long long* nodes) {
 // One wave per channel: P_NLI,i = 16/27 gamma_i^2 R_i sum_k tile(i,k) (eq. gain_fin times R_i),
 // eta_i = P_NLI,i / P_i^3, P_ASE,i = NF_i h f_i R_i / rho(L, f_i), SNR_i (eq. loss).
 __global__ void k_reduce(PlanView pv, const double* __restrict__ P, const double* __restrict__ nf, double snr_trx,
-                         Work w, double* eta, double* pnli_out, double* snr_out, int g_begin, int g_end) {
+                         Work w, double* eta, double* pnli_out, double* snr_out, int g_begin, int g_end,
+                         int n_spans) {
   const int g = g_begin + blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (g >= g_end) return;
   const int b = plan_of_channel(pv, g), o = pv.off[b], n = pv.off[b + 1] - o, i = g - o;
@@ -298,7 +299,7 @@ __global__ void k_reduce(PlanView pv, const double* __restrict__ P, const double
   if (nf) {  // SNR only when noise figures are given (isrsgn_eta passes none)
     double sn = 0.0;
     if (p > 0.0) {
-      const double pase = nf[g] * kH * f * R * exp(-w.ellL[g]);
+      const double pase = nf[g] * kH * f * R * exp(-w.ellL[g]) * n_spans;  // one amplifier per span
       sn = p / (pn + pase);
       if (snr_trx > 0.0) sn = 1.0 / (1.0 / sn + 1.0 / snr_trx);
     }
@@ -420,12 +421,12 @@ hipError_t launch_tiles(const PlanView& pv, const FibreParams& fp, const double*
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_rows(const PlanView& pv, const double* P, const double* nf, double snr_trx, const Work& w,
-                              double* eta, double* pnli_out, double* snr_out, int g_begin, int g_end,
-                              hipStream_t s) {
+hipError_t launch_reduce_rows(const PlanView& pv, const FibreParams& fp, const double* P, const double* nf,
+                              double snr_trx, const Work& w, double* eta, double* pnli_out, double* snr_out,
+                              int g_begin, int g_end, hipStream_t s) {
   if (g_end <= g_begin) return hipSuccess;
   hipLaunchKernelGGL(k_reduce, dim3((g_end - g_begin + 3) / 4), dim3(256), 0, s, pv, P, nf, snr_trx, w, eta,
-                     pnli_out, snr_out, g_begin, g_end);
+                     pnli_out, snr_out, g_begin, g_end, fp.n_spans);
   return hipGetLastError();
 }
 
@@ -438,7 +439,7 @@ hipError_t launch_reduce(const PlanView& pv, const FibreParams& fp, const double
                          double snr_trx, const Work& w, double* eta, double* pnli_out, double* snr_out,
                          double* thr_out, hipStream_t s) {
   (void)fp;
-  hipError_t e = launch_reduce_rows(pv, P, nf, snr_trx, w, eta, pnli_out, snr_out, 0, pv.n_total, s);
+  hipError_t e = launch_reduce_rows(pv, fp, P, nf, snr_trx, w, eta, pnli_out, snr_out, 0, pv.n_total, s);
   if (e != hipSuccess || !thr_out) return e;
   return launch_throughput(pv, P, w, thr_out, s);
 }

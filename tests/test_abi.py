@@ -44,6 +44,7 @@ def _setup(**kw):
     (dict(grid_s=5000), "grid_s"),
     (dict(s_decades=0.0), "s_decades"),
     (dict(ode_sub=0), "ode_sub"),
+    (dict(n_spans=0), "n_spans"),
     (dict(precision=7), "precision"),
     (dict(profile=9), "profile"),
     (dict(beta2=float("nan")), "finite"),

@@ -61,6 +61,14 @@ def test_ode_gradient_matches_duals(prec):
     check_against_duals(wl, prec, dirs)
 
 
+@pytest.mark.parametrize("prec", [W.FP64, W.FP32])
+def test_several_spans_gradient_matches_duals(prec):
+    base = W.random_small(7, seed=33, grid_s=12, grid_v=16, n_steps=16)
+    wl = W.Workload("spans-3", base.fibre.replace(n_spans=3), base.plan.with_power(base.plan.p_w * 20))
+    dirs = [np.eye(7)[c] * wl.plan.p_w[c] for c in (0, 3, 6)]
+    check_against_duals(wl, prec, dirs)
+
+
 def test_gradient_with_guard_channels_and_transceiver():
     wl = W.random_small(8, seed=12, grid_s=16, grid_v=16, n_steps=16)
     p = wl.plan.p_w * 20

@@ -93,6 +93,15 @@ def test_guard_channels(prec):
     check(wl.with_plan(wl.plan.with_power(p)), prec)
 
 
+@pytest.mark.parametrize("prec", [W.FP64, W.FP32])
+def test_several_spans_match_oracle(prec):
+    """n identical spans: the library's phased-array factor per node and n-fold ASE against the
+    oracle's explicit sum over the spans' fields."""
+    base = W.random_small(8, seed=31, grid_s=16, grid_v=24, n_steps=24)
+    for n in (2, 5):
+        check(W.Workload(f"{base.name}-{n}-spans", base.fibre.replace(n_spans=n), base.plan), prec)
+
+
 def test_transceiver_noise():
     wl = W.config_tiny(grid_s=32, grid_v=32)
     plan = wl.plan
