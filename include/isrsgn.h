@@ -122,7 +122,15 @@ int isrsgn_snr(isrsgn_fibre* h, const isrsgn_plan* plan, const double* P_w_dev, 
 
 /* isrsgn_snr plus the exact gradient of each plan's throughput with respect to every
  * launch power, through the PSD products and the power profile (adjoint method).
- *   dthr_dP_dev[n_ch_total] d thr_b / d P_k in bit/s/W for k in plan b */
+ *   dthr_dP_dev[n_ch_total] d thr_b / d P_k in bit/s/W for k in plan b
+ * Workspace: the forward keeps S of eq. (psi_fin) per integration node (8 bytes per node in
+ * the FP32 form, 16 in the FP64 form) for one batch of COI rows at a time, so the adjoint
+ * does not evaluate the step terms twice.  The handle allocates it per plan on the first
+ * gradient call for that plan, at most ISRSGN_STORE_MB MiB (environment, default 16384; 0
+ * keeps no store), and splits the rows into as many batches as that bound needs; it lives
+ * until isrsgn_destroy.  If a row does not fit or the allocation fails, the adjoint
+ * recomputes S instead (same result, slower).  ISRSGN_ENOMEM if the adjoint's other
+ * buffers (O(n_ch_total * n_steps) doubles) cannot be allocated. */
 int isrsgn_snr_grad(isrsgn_fibre* h, const isrsgn_plan* plan, const double* P_w_dev, const double* nf_lin_dev,
                     double snr_trx_lin, double* snr_dev, double* thr_bps_dev, double* dthr_dP_dev,
                     void* hip_stream);
@@ -155,7 +163,7 @@ int isrsgn_stage_times(isrsgn_fibre* h, double* ms_out, int n);
  * (waits for it): [0] nodes evaluated (nodes on the channel support of non-empty rows),
  * [1] node-steps = nodes * n_steps, [2] tiles, [3] index of the tile-kernel variant the
  * autotuner chose (ISRSGN_TILE_VARIANT in the environment forces one; ISRSGN_TUNE_CACHE
- * names a file that keeps the choices across processes), [4] batches of COI rows of an FP32
+ * names a file that keeps the choices across processes), [4] batches of COI rows of a
  * gradient with the per-node store (0: the adjoint recomputed S; the store is bounded by
  * ISRSGN_STORE_MB in the environment, default 16384 MiB, 0 disables it).  n is the capacity of
  * out (up to 5). */
