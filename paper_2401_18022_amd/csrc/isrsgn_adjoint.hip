@@ -86,35 +86,46 @@ __host__ __device__ inline size_t adjoint_lds_bytes(int nmax, int gs, int M, int
          adj_waves(prec) * 7 * kMetaStride * 4 + 16;
 }
 
-// Pass 2 of the FP32 form for one chunk of MC steps at a fixed accuracy tier:
-// out[mm * 65] = cq Re(conj(S) term_{m0+mm}).
-template <bool kLinear, int kTier, int MC>
-__device__ inline void stage_chunk32(const Term32& t, bool valid, int m0, int M, float cq, float sr, float si,
-                                     const StepLds* __restrict__ st, const Col4* __restrict__ col,
+// Pass 2 of the FP32 form for one chunk of MC steps: out[mm * 65] = cq Re(conj(S) term_{m0+mm}),
+// each step in the form of the wave's range it falls in (zero past the last step).
+template <bool kLinear, int kTier>
+__device__ inline void stage_range32(const Term32& t, int m0, int ma, int mb, float cq, float sr, float si,
+                                     const StepLds* __restrict__ st, const Col4* __restrict__ col, const Tab32& tab,
+                                     int n, float* out) {
+#pragma unroll 2
+  for (int m = ma; m < mb; ++m) {
+    const float2 a = term32<kLinear, kTier>(t, m, st, col, tab, n);
+    out[(m - m0) * 65] = cq * fmaf(sr, a.x, si * a.y);
+  }
+}
+
+template <bool kLinear, int MC>
+__device__ inline void stage_chunk32(const Term32& t, bool valid, const Split32& sp, int m0, int M, float cq, float sr,
+                                     float si, const StepLds* __restrict__ st, const Col4* __restrict__ col,
                                      const Tab32& tab, int n, float* out) {
   if (!valid) {  // one branch per chunk, not per step
 #pragma unroll
     for (int mm = 0; mm < MC; ++mm) out[mm * 65] = 0.0f;
     return;
   }
-  if (kTier == kTierLarge) cq *= t.inv_piphr;  // the large tier's terms leave out 1 / (pi phr)
-  if (m0 + MC <= M) {
-#pragma unroll 2
-    for (int mm = 0; mm < MC; ++mm) {
-      const float2 a = term32<kLinear, kTier>(t, m0 + mm, st, col, tab, n);
-      out[mm * 65] = cq * fmaf(sr, a.x, si * a.y);
-    }
+  const int m1 = min(m0 + MC, M);
+  if (sp.small) {
+    stage_range32<kLinear, kTierSmall>(t, m0, m0, m1, cq, sr, si, st, col, tab, n, out);
   } else {
-    for (int mm = 0; mm < MC; ++mm) {
-      const int m = m0 + mm;
-      float qv = 0.0f;
-      if (m < M) {
-        const float2 a = term32<kLinear, kTier>(t, m, st, col, tab, n);
-        qv = cq * fmaf(sr, a.x, si * a.y);
+    const int pe = max(m0, min(sp.m_lo, m1)), xe = max(pe, min(sp.m_hi, m1));
+    if (pe > m0) stage_range32<kLinear, kTierPoly>(t, m0, m0, pe, cq, sr, si, st, col, tab, n, out);
+    if (xe > pe) stage_range32<kLinear, kTierMixed>(t, m0, pe, xe, cq, sr, si, st, col, tab, n, out);
+    if (m1 > xe) {  // edge form: terms carry 2 pi phr
+      const float c = cq * 0.5f * t.inv_piphr;
+      float2 e = lower_edge_phasor32(t.phr, st, xe);
+#pragma unroll 2
+      for (int m = xe; m < m1; ++m) {
+        const float2 a = term32_edge<kLinear>(t, m, st, col, tab, n, e);
+        out[(m - m0) * 65] = c * fmaf(sr, a.x, si * a.y);
       }
-      out[mm * 65] = qv;
     }
   }
+  for (int m = m1; m < m0 + MC; ++m) out[(m - m0) * 65] = 0.0f;
 }
 
 struct AdjArgs {
@@ -175,7 +186,7 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
     }
     if (b != cur_b) {
       load_channels(ch, pv, A.P, o, n);
-      if (kPrec == 0) load_steps(steps, A.w.zm + (size_t)b * M, A.w.hdz32 + (size_t)b * M, M);
+      if (kPrec == 0) load_steps(steps, A.w.zm + (size_t)b * M, A.w.dz + (size_t)b * M, A.w.hdz32 + (size_t)b * M, M);
       cur_b = b;
     }
     if (kPrec == 0) load_cols<kLinear>(col, A.w.lt32 + (size_t)M * o, n, M, i, k);
@@ -247,14 +258,11 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
         const bool wave_two_valued = !wave_one_run && __all(two_valued);
         // pass 1: S
         real sr = 0, si = 0;
-        Term32 t32;
+        Term32 t32{};
         Term64 t64;
-        bool tsmall = true, tlarge = true;  // invalid lanes do not restrict the wave's tier
-        if (valid && kPrec == 0) {
-          t32 = term32_setup(nd, k, n);
-          node_tier_flags(t32, steps, M, &tsmall, &tlarge);
-        }
-        const int tier = wave_tier(tsmall, tlarge);
+        if (valid && kPrec == 0) t32 = term32_setup(nd, k, n);
+        Split32 sp{};
+        if (kPrec == 0) sp = wave_split(valid, t32, steps, M);
         if (valid) {
           if (kStored) {
             const int64_t slot = ((int64_t)(t - A.t_begin) * 3 + part) * nodes + q;
@@ -271,9 +279,7 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
           } else if (kPrec == 0) {
             const Tab32 tab = make_tab32(A.w.lt32 + (size_t)M * o, n, M);
             float a32, b32;
-            if (tier == kTierSmall) accumulate32<kLinear, kTierSmall, 4>(t32, steps, col, tab, n, M, &a32, &b32);
-            else if (tier == kTierLarge) accumulate32<kLinear, kTierLarge, 4>(t32, steps, col, tab, n, M, &a32, &b32);
-            else accumulate32<kLinear, kTierMixed, 4>(t32, steps, col, tab, n, M, &a32, &b32);
+            accumulate32<kLinear, 4>(t32, sp, steps, col, tab, n, M, &a32, &b32);
             sr = a32;
             si = b32;
           } else {
@@ -297,12 +303,7 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
           if (kPrec == 0) {
             const Tab32 tab = make_tab32(A.w.lt32 + (size_t)M * o, n, M);
             float* out = reinterpret_cast<float*>(my_stage) + lane;
-            if (tier == kTierSmall)
-              stage_chunk32<kLinear, kTierSmall, MC>(t32, valid, m0, M, (float)cq, (float)sr, (float)si, steps, col, tab, n, out);
-            else if (tier == kTierLarge)
-              stage_chunk32<kLinear, kTierLarge, MC>(t32, valid, m0, M, (float)cq, (float)sr, (float)si, steps, col, tab, n, out);
-            else
-              stage_chunk32<kLinear, kTierMixed, MC>(t32, valid, m0, M, (float)cq, (float)sr, (float)si, steps, col, tab, n, out);
+            stage_chunk32<kLinear, MC>(t32, valid, sp, m0, M, (float)cq, (float)sr, (float)si, steps, col, tab, n, out);
           } else {
             for (int mm = 0; mm < MC; ++mm) {
               const int m = m0 + mm;

@@ -368,6 +368,7 @@ __device__ inline bool make_node(const ChanLds& ch, const RowLds& rw, const Tile
 // Per-step data of the current plan, staged in LDS and read with uniform addresses.
 struct StepLds {
   double zm;   // step midpoint z_m
+  double zu;   // upper edge z_m + dz_m / 2 (the lower edge of step 0 is z = 0)
   float hdz;   // dz_m / 2
   float zmf;   // z_m in FP32 (small-phase tier)
   float dz;    // dz_m
@@ -430,10 +431,12 @@ __device__ inline void load_cols(Col4* col, const float2* __restrict__ tab, int 
   }
 }
 
-__device__ inline void load_steps(StepLds* st, const double* __restrict__ zm, const float* __restrict__ hdz, int M) {
+__device__ inline void load_steps(StepLds* st, const double* __restrict__ zm, const double* __restrict__ dz,
+                                  const float* __restrict__ hdz, int M) {
   for (int m = threadIdx.x; m < M; m += blockDim.x) {
     StepLds v;
     v.zm = zm[m];
+    v.zu = zm[m] + 0.5 * dz[m];
     v.hdz = hdz[m];
     v.zmf = (float)zm[m];
     v.dz = 2.0f * hdz[m];
@@ -462,20 +465,42 @@ __device__ inline float2 tab32_at(const Tab32& t, unsigned voff, unsigned soff) 
   return make_float2(__uint_as_float(v[0]), __uint_as_float(v[1]));
 }
 
-// Accuracy tiers of the FP32 step term, chosen per wave (all its lanes must qualify):
-//   kTierSmall: |phi| z_max < 1/4 revolution and |phi dz_m / 2| < 1/2 at every step: the phase
-//               is formed in FP32 (error < 5e-8 revolutions) and the sinc factor is its Taylor
-//               polynomial -- no FP64 and one transcendental fewer;
-//   kTierLarge: |phi dz_m / 2| >= 1/2 at every step: FP64 phase, sinc from the hardware sine;
-//   kTierMixed: FP64 phase, polynomial or sine chosen per step.
-enum { kTierMixed = 0, kTierSmall = 1, kTierLarge = 2 };
+// Evaluation forms of the FP32 step term.  Along the steps dz_m grows (equal power decrement),
+// so each node has a first step m_s from which |phi dz_m / 2| >= 1/2 ("sine steps"); before it
+// the sinc factor is its Taylor polynomial.  A wave runs its nodes' steps in up to three ranges,
+// each in one form for all lanes (m_lo, m_hi: the smallest and largest m_s of the wave):
+//   kTierSmall: every node has |phi| z_max < 1/4 revolution and no sine step: phase formed in
+//               FP32 (error < 5e-8 revolutions), polynomial sinc -- no FP64;
+//   kTierPoly:  steps [0, m_lo): FP64 phase, polynomial sinc;
+//   kTierMixed: steps [m_lo, m_hi): FP64 phase, polynomial or sine chosen per lane;
+//   edge form:  steps [m_hi, M): every lane is past m_s.  Since z_m is the step midpoint,
+//               dz_m sinc(phi dz_m / 2) e^(j phi z_m) = (E_(m+1) - E_m) / (j phi) with the edge
+//               phasors E = e^(j phi z) at z_m -+ dz_m / 2 (the exact integral of e^(j phi z)
+//               over the step), so one sine/cosine pair per step, carried from step to step,
+//               replaces the phase pair and the sinc sine.
+enum { kTierMixed = 0, kTierSmall = 1, kTierPoly = 2 };
+
+// Exponent log2 p_m of eq. (pk) from the scaled FP32 profile table (f1, f2 segments) and the
+// tile's column pair (f3, f_i).
+template <bool kLinear>
+__device__ inline float log2p32(const Term32& q, int m, float2 cab, const Tab32& tab, int n) {
+  const float e3 = fmaf(q.t3, cab.y, cab.x);
+  if (kLinear) return e3;
+  const unsigned row = (unsigned)m * (unsigned)n * (unsigned)sizeof(float2);
+  const float2 l1 = tab32_at(tab, q.o1, row), l2 = tab32_at(tab, q.o2, row);
+  return fmaf(q.t1, l1.y, l1.x) + fmaf(q.t2, l2.y, l2.x) + e3;
+}
+
+// Column pair of step m for this node: the f3 term uses one of the two segments (fixed per node).
+__device__ inline float2 col_pair(const Term32& q, const Col4* __restrict__ col, int m) {
+  return reinterpret_cast<const float2*>(col + m)[q.up3 ? 1 : 0];
+}
 
 template <bool kLinear, int kTier>
 __device__ inline float2 term32(const Term32& q, int m, const StepLds* __restrict__ st, const Col4* __restrict__ col,
                                 const Tab32& tab, int n) {
   const StepLds sv = st[m];
-  // the f3 term uses one of the two column segments (fixed per node): load only that pair
-  const float2 cab = reinterpret_cast<const float2*>(col + m)[q.up3 ? 1 : 0];
+  const float2 cab = col_pair(q, col, m);
   float fr;
   if (kTier == kTierSmall) {
     fr = q.phrf * sv.zmf;  // |phr z_m| < 1/4 at every step of this tier: already reduced
@@ -485,63 +510,132 @@ __device__ inline float2 term32(const Term32& q, int m, const StepLds* __restric
   }
   const float sn = __builtin_amdgcn_sinf(fr);
   const float cs = __builtin_amdgcn_cosf(fr);
-  // Amplitude dz_m sinc(phi dz_m / 2).  The large tier returns sin(phi dz_m / 2) without the
-  // per-node factor 1 / (pi phr): its callers apply that factor once per node.
-  float amp0;
-  if (kTier != kTierLarge) {
-    const float u2 = q.phrf2 * sv.c2;
-    amp0 = sv.dz * fmaf(u2, fmaf(u2, fmaf(u2, -1.0f / 5040.0f, 1.0f / 120.0f), -1.0f / 6.0f), 1.0f);
-    if (kTier == kTierMixed) {  // both forms, then a per-lane select (no branch)
-      const float hh = q.phrf * sv.hdz;
-      const float as = __builtin_amdgcn_sinf(hh - rintf(hh)) * q.inv_piphr;
-      amp0 = u2 < 0.25f ? amp0 : as;
-    }
-  } else {
+  // amplitude dz_m sinc(phi dz_m / 2)
+  const float u2 = q.phrf2 * sv.c2;
+  float amp0 = sv.dz * fmaf(u2, fmaf(u2, fmaf(u2, -1.0f / 5040.0f, 1.0f / 120.0f), -1.0f / 6.0f), 1.0f);
+  if (kTier == kTierMixed) {  // both forms, then a per-lane select (no branch)
     const float hh = q.phrf * sv.hdz;
-    amp0 = __builtin_amdgcn_sinf(hh - rintf(hh));
+    const float as = __builtin_amdgcn_sinf(hh - rintf(hh)) * q.inv_piphr;
+    amp0 = u2 < 0.25f ? amp0 : as;
   }
-  const float e3 = fmaf(q.t3, cab.y, cab.x);
-  float e2;
-  if (kLinear) {
-    e2 = e3;
-  } else {
-    const unsigned row = (unsigned)m * (unsigned)n * (unsigned)sizeof(float2);
-    const float2 l1 = tab32_at(tab, q.o1, row), l2 = tab32_at(tab, q.o2, row);
-    e2 = fmaf(q.t1, l1.y, l1.x) + fmaf(q.t2, l2.y, l2.x) + e3;
-  }
-  const float amp = __builtin_amdgcn_exp2f(e2) * amp0;
+  const float amp = __builtin_amdgcn_exp2f(log2p32<kLinear>(q, m, cab, tab, n)) * amp0;
   return make_float2(amp * cs, amp * sn);
 }
 
-// Tier of one node from the plan's step extremes (LDS: steps grow with m).
-__device__ inline void node_tier_flags(const Term32& q, const StepLds* st, int M, bool* small, bool* large) {
-  const float ap = fabsf(q.phrf), tp = 2.0f * (float)kPi;
-  *small = ap * st[M - 1].zmf < 0.25f && tp * ap * st[M - 1].hdz < 0.5f;
-  *large = tp * ap * st[0].hdz >= 0.5f;
+// (cos, sin) of 2 pi phr z at a step edge, the FP64 phase reduced to [-1/2, 1/2) revolutions.
+__device__ inline float2 edge_phasor32(double phr, double z) {
+  const float fr = (float)__builtin_amdgcn_fract(fma(phr, z, 0.5)) - 0.5f;
+  return make_float2(__builtin_amdgcn_cosf(fr), __builtin_amdgcn_sinf(fr));
 }
 
-// Wave-uniform tier: every active lane must qualify.
-__device__ inline int wave_tier(bool small, bool large) {
-  if (__all(small)) return kTierSmall;
-  if (__all(large)) return kTierLarge;
-  return kTierMixed;
+// Phasor at the lower edge of step m.
+__device__ inline float2 lower_edge_phasor32(double phr, const StepLds* __restrict__ st, int m) {
+  return m > 0 ? edge_phasor32(phr, st[m - 1].zu) : make_float2(1.0f, 0.0f);
 }
 
+// Step m in edge form, as 2 pi phr times its term: p_m (E_(m+1) - E_m) / j.  e holds E_m on
+// entry and E_(m+1) on return.
+template <bool kLinear>
+__device__ inline float2 term32_edge(const Term32& q, int m, const StepLds* __restrict__ st,
+                                     const Col4* __restrict__ col, const Tab32& tab, int n, float2& e) {
+  const double zu = st[m].zu;
+  const float2 cab = col_pair(q, col, m);
+  const float2 e1 = edge_phasor32(q.phr, zu);
+  const float p = __builtin_amdgcn_exp2f(log2p32<kLinear>(q, m, cab, tab, n));
+  const float2 r = make_float2(p * (e1.y - e.y), p * (e.x - e1.x));
+  e = e1;
+  return r;
+}
 
-// S = sum of the step terms of one node at a fixed tier.
-template <bool kLinear, int kTier, int kUnroll>
-__device__ inline void accumulate32(const Term32& q, const StepLds* __restrict__ st, const Col4* __restrict__ col,
-                                    const Tab32& tab, int n, int M, float* sr, float* si) {
-  float a = 0.0f, b = 0.0f;
-#pragma unroll kUnroll
-  for (int m = 0; m < M; ++m) {
-    const float2 t = term32<kLinear, kTier>(q, m, st, col, tab, n);
-    a += t.x;
-    b += t.y;
+// First sine step m_s of a node (M if none): the same test as the mixed form's select.
+__device__ inline int sine_step(const Term32& q, const StepLds* __restrict__ st, int M) {
+  if (q.phrf2 * st[0].c2 >= 0.25f) return 0;
+  if (q.phrf2 * st[M - 1].c2 < 0.25f) return M;
+  int lo = 1, hi = M - 1;  // the answer lies in [1, M - 1]
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (q.phrf2 * st[mid].c2 < 0.25f) lo = mid + 1;
+    else hi = mid;
   }
-  if (kTier == kTierLarge) {
-    a *= q.inv_piphr;
-    b *= q.inv_piphr;
+  return lo;
+}
+
+// Whether a node qualifies for the FP32-phase form (plan's last step: largest z and dz).
+__device__ inline bool node_small(const Term32& q, const StepLds* st, int M) {
+  const float ap = fabsf(q.phrf), tp = 2.0f * (float)kPi;
+  return ap * st[M - 1].zmf < 0.25f && tp * ap * st[M - 1].hdz < 0.5f;
+}
+
+// The wave's ranges.  Every lane of the wave must be active; lanes without a node pass
+// active = false and do not restrict the result.
+struct Split32 {
+  bool small;      // kTierSmall for all steps
+  int m_lo, m_hi;  // 0 <= m_lo <= m_hi <= M
+};
+
+__device__ inline Split32 wave_split(bool active, const Term32& q, const StepLds* st, int M) {
+  Split32 r;
+  r.small = __all(!active || node_small(q, st, M));
+  if (r.small) {
+    r.m_lo = r.m_hi = M;
+    return r;
+  }
+  int lo = M, hi = 0;
+  if (active) lo = hi = sine_step(q, st, M);
+#pragma unroll
+  for (int sh = 1; sh < 64; sh <<= 1) {
+    lo = min(lo, __shfl_xor(lo, sh));
+    hi = max(hi, __shfl_xor(hi, sh));
+  }
+  // equal in every lane after the butterfly: scalar registers, so the range loops are uniform
+  // (their table loads keep a scalar row offset)
+  lo = __builtin_amdgcn_readfirstlane(lo);
+  hi = __builtin_amdgcn_readfirstlane(hi);
+  r.m_lo = lo;
+  r.m_hi = hi > lo ? hi : lo;
+  return r;
+}
+
+// Sum of the step terms over [m0, m1) in form kTier (not the edge form).
+template <bool kLinear, int kTier, int kUnroll>
+__device__ inline void accumulate_range32(const Term32& q, const StepLds* __restrict__ st, const Col4* __restrict__ col,
+                                          const Tab32& tab, int n, int m0, int m1, float* a, float* b) {
+  float x = 0.0f, y = 0.0f;
+#pragma unroll kUnroll
+  for (int m = m0; m < m1; ++m) {
+    const float2 t = term32<kLinear, kTier>(q, m, st, col, tab, n);
+    x += t.x;
+    y += t.y;
+  }
+  *a += x;
+  *b += y;
+}
+
+// S of one node: the wave's ranges in order, the edge range scaled by 1 / (2 pi phr) at the end.
+template <bool kLinear, int kUnroll>
+__device__ inline void accumulate32(const Term32& q, const Split32& sp, const StepLds* __restrict__ st,
+                                    const Col4* __restrict__ col, const Tab32& tab, int n, int M, float* sr,
+                                    float* si) {
+  float a = 0.0f, b = 0.0f;
+  if (sp.small) {
+    accumulate_range32<kLinear, kTierSmall, kUnroll>(q, st, col, tab, n, 0, M, &a, &b);
+  } else {
+    if (sp.m_lo > 0) accumulate_range32<kLinear, kTierPoly, kUnroll>(q, st, col, tab, n, 0, sp.m_lo, &a, &b);
+    if (sp.m_hi > sp.m_lo)
+      accumulate_range32<kLinear, kTierMixed, kUnroll>(q, st, col, tab, n, sp.m_lo, sp.m_hi, &a, &b);
+    if (sp.m_hi < M) {
+      float2 e = lower_edge_phasor32(q.phr, st, sp.m_hi);
+      float x = 0.0f, y = 0.0f;
+#pragma unroll kUnroll
+      for (int m = sp.m_hi; m < M; ++m) {
+        const float2 t = term32_edge<kLinear>(q, m, st, col, tab, n, e);
+        x += t.x;
+        y += t.y;
+      }
+      const float h = 0.5f * q.inv_piphr;
+      a = fmaf(h, x, a);
+      b = fmaf(h, y, b);
+    }
   }
   *sr = a;
   *si = b;

@@ -214,7 +214,7 @@ k_tiles(TileArgs A) {
     const double* dz = A.w.dz + (size_t)b * M;
     if (b != cur_b) {
       load_channels(ch, pv, A.P, o, n);
-      if (kPrec == 0) load_steps(steps, zm, A.w.hdz32 + (size_t)b * M, M);
+      if (kPrec == 0) load_steps(steps, zm, dz, A.w.hdz32 + (size_t)b * M, M);
       cur_b = b;
     }
     if (kPrec == 0) load_cols<kLinear>(col, A.w.lt32 + (size_t)M * o, n, M, i, k);
@@ -226,24 +226,25 @@ k_tiles(TileArgs A) {
       if (!layout_rows(rw, g, part, GS, GV, A.fp.s_decades)) continue;
       __syncthreads();
       const int64_t nodes = (int64_t)GS * GV;
-      for (int64_t q = tid; q < nodes; q += kTileBlock) {
+      // whole waves stay in the loop (the FP32 form plans its step ranges across the wave)
+      for (int64_t base = 0; base < nodes; base += kTileBlock) {
+        const int64_t q = base + tid;
         Node nd;
-        if (!make_node(ch, rw, g, n, k, part, (int)(q / GV), (int)(q % GV), A.fp, &nd)) continue;
+        const bool valid = q < nodes && make_node(ch, rw, g, n, k, part, (int)(q / GV), (int)(q % GV), A.fp, &nd);
         double s2v;
         if (kPrec == 0) {
-          const Term32 tq = term32_setup(nd, k, n);
+          Term32 tq{};
+          if (valid) tq = term32_setup(nd, k, n);
+          const Split32 sp = wave_split(valid, tq, steps, M);
+          if (!valid) continue;
           const Tab32 tab = make_tab32(A.w.lt32 + (size_t)M * o, n, M);
-          bool small, large;
-          node_tier_flags(tq, steps, M, &small, &large);
-          const int tier = wave_tier(small, large);
           float sr, si;
-          if (tier == kTierSmall) accumulate32<kLinear, kTierSmall, kUnroll>(tq, steps, col, tab, n, M, &sr, &si);
-          else if (tier == kTierLarge) accumulate32<kLinear, kTierLarge, kUnroll>(tq, steps, col, tab, n, M, &sr, &si);
-          else accumulate32<kLinear, kTierMixed, kUnroll>(tq, steps, col, tab, n, M, &sr, &si);
+          accumulate32<kLinear, kUnroll>(tq, sp, steps, col, tab, n, M, &sr, &si);
           s2v = (double)sr * sr + (double)si * si;
           if (A.w.s_store)
             static_cast<float2*>(A.w.s_store)[((int64_t)(t - A.t_begin) * 3 + part) * nodes + q] = make_float2(sr, si);
         } else {
+          if (!valid) continue;
           const Term64 tq = term64_setup(nd, i);
           const double* tab = A.w.ell64 + (size_t)M * o;
           double sr = 0.0, si = 0.0;
