@@ -165,8 +165,9 @@ int isrsgn_stage_times(isrsgn_fibre* h, double* ms_out, int n);
  * autotuner chose (ISRSGN_TILE_VARIANT in the environment forces one; ISRSGN_TUNE_CACHE
  * names a file that keeps the choices across processes), [4] batches of COI rows of a
  * gradient with the per-node store (0: the adjoint recomputed S; the store is bounded by
- * ISRSGN_STORE_MB in the environment, default 16384 MiB, 0 disables it).  n is the capacity of
- * out (up to 5). */
+ * ISRSGN_STORE_MB in the environment, default 16384 MiB, 0 disables it), [5] plans whose FP32
+ * step terms used the low-rank form of the ODE profile table (the rest read the table), [6] the
+ * most terms any of them needed.  n is the capacity of out (up to 7). */
 int isrsgn_work_counts(isrsgn_fibre* h, double* out, int n);
 
 /* Frees the handle and its device memory (waits for its outstanding work).  NULL is allowed. */

@@ -235,9 +235,10 @@ class Engine:
         return dict(zip(["profile", "tiles", "reduce", "adjoint_tiles", "adjoint_rest", "total"], out.tolist()))
 
     def work_counts(self) -> dict:
-        out = np.zeros(5)
-        _check(lib().isrsgn_work_counts(self.h, out.ctypes.data_as(_dp), 5))
-        return dict(nodes=out[0], node_steps=out[1], tiles=out[2], variant=int(out[3]), grad_batches=int(out[4]))
+        out = np.zeros(7)
+        _check(lib().isrsgn_work_counts(self.h, out.ctypes.data_as(_dp), 7))
+        return dict(nodes=out[0], node_steps=out[1], tiles=out[2], variant=int(out[3]), grad_batches=int(out[4]),
+                    lowrank_plans=int(out[5]), lowrank_terms=int(out[6]))
 
 
 def tiles_to_blocks(tiles, plan: W.Plan):

@@ -81,28 +81,29 @@ struct AdjCfg<1> {
 __host__ __device__ inline size_t adjoint_lds_bytes(int nmax, int gs, int M, int prec) {
   const int mc = prec == 0 ? 16 : 8;
   const size_t rb = prec == 0 ? 4 : 8;
-  return sizeof(double) * (4 * (size_t)nmax + 4 * (size_t)gs + (size_t)nmax + 6 * (size_t)M + 8) +
+  // (+1 double: the step tables start on a 16-byte boundary)
+  return sizeof(double) * (4 * (size_t)nmax + 4 * (size_t)gs + (size_t)nmax + 6 * (size_t)M + 8 + 1) +
          (sizeof(StepLds) + sizeof(Col4)) * (size_t)M + adj_waves(prec) * (size_t)mc * 65 * rb +
          adj_waves(prec) * 7 * kMetaStride * 4 + 16;
 }
 
 // Pass 2 of the FP32 form for one chunk of MC steps: out[mm * 65] = cq Re(conj(S) term_{m0+mm}),
 // each step in the form of the wave's range it falls in (zero past the last step).
-template <bool kLinear, int kTier>
+template <bool kLinear, int kTier, class Src>
 __device__ inline void stage_range32(const Term32& t, int m0, int ma, int mb, float cq, float sr, float si,
-                                     const StepLds* __restrict__ st, const Col4* __restrict__ col, const Tab32& tab,
-                                     int n, float* out) {
+                                     const StepLds* __restrict__ st, const Col4* __restrict__ col, const Src& src,
+                                     float* out) {
 #pragma unroll 2
   for (int m = ma; m < mb; ++m) {
-    const float2 a = term32<kLinear, kTier>(t, m, st, col, tab, n);
+    const float2 a = term32<kLinear, kTier>(t, m, st, col, src);
     out[(m - m0) * 65] = cq * fmaf(sr, a.x, si * a.y);
   }
 }
 
-template <bool kLinear, int MC>
+template <bool kLinear, int MC, class Src>
 __device__ inline void stage_chunk32(const Term32& t, bool valid, const Split32& sp, int m0, int M, float cq, float sr,
                                      float si, const StepLds* __restrict__ st, const Col4* __restrict__ col,
-                                     const Tab32& tab, int n, float* out) {
+                                     const Src& src, float* out) {
   if (!valid) {  // one branch per chunk, not per step
 #pragma unroll
     for (int mm = 0; mm < MC; ++mm) out[mm * 65] = 0.0f;
@@ -110,17 +111,17 @@ __device__ inline void stage_chunk32(const Term32& t, bool valid, const Split32&
   }
   const int m1 = min(m0 + MC, M);
   if (sp.small) {
-    stage_range32<kLinear, kTierSmall>(t, m0, m0, m1, cq, sr, si, st, col, tab, n, out);
+    stage_range32<kLinear, kTierSmall>(t, m0, m0, m1, cq, sr, si, st, col, src, out);
   } else {
     const int pe = max(m0, min(sp.m_lo, m1)), xe = max(pe, min(sp.m_hi, m1));
-    if (pe > m0) stage_range32<kLinear, kTierPoly>(t, m0, m0, pe, cq, sr, si, st, col, tab, n, out);
-    if (xe > pe) stage_range32<kLinear, kTierMixed>(t, m0, pe, xe, cq, sr, si, st, col, tab, n, out);
+    if (pe > m0) stage_range32<kLinear, kTierPoly>(t, m0, m0, pe, cq, sr, si, st, col, src, out);
+    if (xe > pe) stage_range32<kLinear, kTierMixed>(t, m0, pe, xe, cq, sr, si, st, col, src, out);
     if (m1 > xe) {  // edge form: terms carry 2 pi phr
       const float c = cq * 0.5f * t.inv_piphr;
       float2 e = lower_edge_phasor32(t.phr, st, xe);
 #pragma unroll 2
       for (int m = xe; m < m1; ++m) {
-        const float2 a = term32_edge<kLinear>(t, m, st, col, tab, n, e);
+        const float2 a = term32_edge<kLinear>(t, m, st, col, src, e);
         out[(m - m0) * 65] = c * fmaf(sr, a.x, si * a.y);
       }
     }
@@ -159,6 +160,7 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
   d += 6 * M;
   double* red = d;
   d += 8;
+  d += (d - reinterpret_cast<double*>(smem_raw)) & 1;  // 16-byte boundary for the step tables
   StepLds* steps = reinterpret_cast<StepLds*>(d);
   Col4* col = reinterpret_cast<Col4*>(steps + M);
   real* stage = reinterpret_cast<real*>(col + M);  // [waves][MC][65] (odd row stride: no bank conflicts)
@@ -263,6 +265,9 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
         if (valid && kPrec == 0) t32 = term32_setup(nd, k, n);
         Split32 sp{};
         if (kPrec == 0) sp = wave_split(valid, t32, steps, M);
+        // the f1 + f2 profile terms of the FP32 form: table gathers (the staging and re-map keep
+        // the LDS busy, so the low-rank form of the forward kernel does not pay here)
+        const Gather32 gsrc{make_tab32(A.w.lt32 + (size_t)M * o, n, M), n};
         if (valid) {
           if (kStored) {
             const int64_t slot = ((int64_t)(t - A.t_begin) * 3 + part) * nodes + q;
@@ -277,9 +282,8 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
             }
             if (kPrec == 1) t64 = term64_setup(nd, i);
           } else if (kPrec == 0) {
-            const Tab32 tab = make_tab32(A.w.lt32 + (size_t)M * o, n, M);
             float a32, b32;
-            accumulate32<kLinear, 4>(t32, sp, steps, col, tab, n, M, &a32, &b32);
+            accumulate32<kLinear, 4>(t32, sp, steps, col, gsrc, M, &a32, &b32);
             sr = a32;
             si = b32;
           } else {
@@ -301,9 +305,8 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
         // pass 2 in chunks of MC steps
         for (int m0 = 0; m0 < M; m0 += MC) {
           if (kPrec == 0) {
-            const Tab32 tab = make_tab32(A.w.lt32 + (size_t)M * o, n, M);
             float* out = reinterpret_cast<float*>(my_stage) + lane;
-            stage_chunk32<kLinear, MC>(t32, valid, sp, m0, M, (float)cq, (float)sr, (float)si, steps, col, tab, n, out);
+            stage_chunk32<kLinear, MC>(t32, valid, sp, m0, M, (float)cq, (float)sr, (float)si, steps, col, gsrc, out);
           } else {
             for (int mm = 0; mm < MC; ++mm) {
               const int m = m0 + mm;
@@ -623,6 +626,8 @@ int adjoint_blocks_per_cu(const FibreParams& fp, int nmax, bool stored) {
     else k = fp.profile == 0 ? reinterpret_cast<const void*>(k_adjoint<1, true, false>)
                              : reinterpret_cast<const void*>(k_adjoint<1, false, false>);
   }
+  // above 64 KiB the kernel must opt in before the occupancy query counts its blocks
+  if (shm > 65536) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 64 * adj_waves(fp.precision), shm) != hipSuccess || nb < 1)
     nb = 1;
   return nb;

@@ -84,6 +84,7 @@ struct PlanEntry {
   DevBuf d_off, d_toff, d_f, d_R, d_alpha, d_aeff, d_gamma, d_cr;
   // workspace
   DevBuf abar, zm, dz, hdz32, ell64, lt32, ellL, tiles, pnli, snr, counter;
+  DevBuf lr_a, lr_b, lr_rank, lr_res, lr_b64;  // low-rank form of lt32 (FP32 form, ODE profile)
   DevBuf states, state_off, lam, gG, gL, gLL, gP, coef;
   bool grad_ready = false;
   // FP32 gradient: row batches whose per-node S fits the store (see ensure_grad_workspace)
@@ -120,6 +121,11 @@ struct PlanEntry {
     w.hdz32 = hdz32.as<float>();
     w.ell64 = ell64.as<double>();
     w.lt32 = lt32.as<float2>();
+    w.lr_a = lr_a.as<float>();
+    w.lr_b = lr_b.as<float2>();
+    w.lr_rank = lr_rank.as<int>();
+    w.lr_res = lr_res.as<double>();
+    w.lr_b64 = lr_b64.as<double>();
     w.ellL = ellL.as<double>();
     w.tiles = tiles.as<double>();
     w.pnli = pnli.as<double>();
@@ -256,7 +262,10 @@ int get_plan(isrsgn_fibre* h, const isrsgn_plan* p, hipStream_t s, PlanEntry** o
             e->zm.ensure(8 * nb * M) && e->dz.ensure(8 * nb * M) && e->hdz32.ensure(4 * nb * M) &&
             e->ell64.ensure(8 * nt * M) && e->ellL.ensure(8 * nt) && e->tiles.ensure(8 * (size_t)ntiles) &&
             e->pnli.ensure(8 * nt) && e->snr.ensure(8 * nt) && e->counter.ensure(64) &&
-            (h->desc.precision != ISRSGN_FP32 || e->lt32.ensure(8 * nt * M));
+            (h->desc.precision != ISRSGN_FP32 || e->lt32.ensure(8 * nt * M)) &&
+            (h->desc.precision != ISRSGN_FP32 || h->desc.profile != ISRSGN_PROFILE_ODE ||
+             (e->lr_a.ensure(4 * nb * M * kRank) && e->lr_b.ensure(8 * nt * kRank) && e->lr_rank.ensure(4 * nb) &&
+              e->lr_res.ensure(8 * nt * M) && e->lr_b64.ensure(8 * nt * kRank)));
   if (!ok) return fail(ISRSGN_ENOMEM, "device allocation failed for a plan of %d channels", total);
   hipError_t err;
   if ((err = hipMemcpy(e->d_off.p, p->ch_offsets, sizeof(int) * (nb + 1), hipMemcpyHostToDevice)) != hipSuccess ||
@@ -677,6 +686,10 @@ int isrsgn_setup_fibre(const isrsgn_fibre_desc* d, isrsgn_fibre** out) {
   fp.ode_sub = d->ode_sub;
   fp.precision = d->precision;
   fp.n_spans = d->n_spans;
+  {
+    const char* lr = std::getenv("ISRSGN_LOWRANK");
+    fp.lowrank = lr && *lr == '0' ? 0 : 1;
+  }
   fp.s_decades = d->s_decades;
   fp.n_tab = d->n_tab;
   hipError_t err;
@@ -783,7 +796,7 @@ int isrsgn_stage_times(isrsgn_fibre* h, double* ms, int n) {
 int isrsgn_work_counts(isrsgn_fibre* h, double* out, int n) {
   g_err.clear();
   if (!h || !out || n < 1) return fail(ISRSGN_EINVAL, "handle and output are required");
-  for (int q = 0; q < n && q < 5; ++q) out[q] = 0.0;
+  for (int q = 0; q < n && q < 7; ++q) out[q] = 0.0;
   if (n > 3) out[3] = h->last_variant;
   if (h->plans.empty()) return ISRSGN_OK;
   const PlanEntry* e = h->plans[0].get();
@@ -791,6 +804,19 @@ int isrsgn_work_counts(isrsgn_fibre* h, double* out, int n) {
   unsigned long long nodes = 0;
   hipError_t err = hipMemcpy(&nodes, e->counter.as<char>() + 32, sizeof(nodes), hipMemcpyDeviceToHost);
   if (err != hipSuccess) return hip_fail(err, "work counters");
+  if (n > 5 && e->lr_rank.p) {
+    std::vector<int> rk((size_t)e->n_batch);
+    err = hipMemcpy(rk.data(), e->lr_rank.p, sizeof(int) * rk.size(), hipMemcpyDeviceToHost);
+    if (err != hipSuccess) return hip_fail(err, "low-rank counters");
+    int used = 0, most = 0;
+    for (int r : rk)
+      if (r >= 0) {
+        ++used;
+        most = std::max(most, r);
+      }
+    out[5] = used;
+    if (n > 6) out[6] = most;
+  }
   const double v[3] = {(double)nodes, (double)nodes * h->desc.n_steps, (double)e->n_tiles};
   for (int q = 0; q < n && q < 3; ++q) out[q] = v[q];
   return ISRSGN_OK;

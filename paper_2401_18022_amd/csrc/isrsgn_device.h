@@ -480,15 +480,56 @@ __device__ inline float2 tab32_at(const Tab32& t, unsigned voff, unsigned soff) 
 //               replaces the phase pair and the sinc sine.
 enum { kTierMixed = 0, kTierSmall = 1, kTierPoly = 2 };
 
-// Exponent log2 p_m of eq. (pk) from the scaled FP32 profile table (f1, f2 segments) and the
-// tile's column pair (f3, f_i).
-template <bool kLinear>
-__device__ inline float log2p32(const Term32& q, int m, float2 cab, const Tab32& tab, int n) {
+// Sources of the f1 + f2 part of log2 p_m (eq. pk) for the FP32 step terms.
+//   Gather32:  the scaled profile table, interpolated at the node's f1 and f2 segments;
+//   LowRank32: the plan's low-rank form of that table, L(m, c) ~ sum_r a_r(m) b_r(c): per node
+//              c_r = b_r(f1) + b_r(f2) (interpolated like the table -- interpolation commutes
+//              with the factorisation), per step sum_r a_r(m) c_r with a_r(m) from LDS, so the
+//              step loop does no memory gathers.
+struct Gather32 {
+  Tab32 tab;
+  int n;
+  __device__ float e12(const Term32& q, int m) const {
+    const unsigned row = (unsigned)m * (unsigned)n * (unsigned)sizeof(float2);
+    const float2 l1 = tab32_at(tab, q.o1, row), l2 = tab32_at(tab, q.o2, row);
+    return fmaf(q.t1, l1.y, l1.x) + fmaf(q.t2, l2.y, l2.x);
+  }
+};
+
+struct LowRank32 {
+  const float4* __restrict__ a;  // LDS [M][kRank / 4]: a_r(m)
+  float c[kRank];
+  // b: the plan's [channel][kRank] (b_r, b_r(next channel) - b_r)
+  __device__ void setup(const Term32& q, const float2* __restrict__ b) {
+    const float4* b1 = reinterpret_cast<const float4*>(b + (size_t)(q.o1 / sizeof(float2)) * kRank);
+    const float4* b2 = reinterpret_cast<const float4*>(b + (size_t)(q.o2 / sizeof(float2)) * kRank);
+#pragma unroll
+    for (int j = 0; j < kRank / 2; ++j) {
+      const float4 u = b1[j], v = b2[j];
+      c[2 * j] = fmaf(q.t1, u.y, u.x) + fmaf(q.t2, v.y, v.x);
+      c[2 * j + 1] = fmaf(q.t1, u.w, u.z) + fmaf(q.t2, v.w, v.z);
+    }
+  }
+  // smallest terms first; the same order as the factorisation's FP32 check
+  __device__ float e12(const Term32&, int m) const {
+    float e = 0.0f;
+#pragma unroll
+    for (int j = kRank / 4 - 1; j >= 0; --j) {
+      const float4 v = a[m * (kRank / 4) + j];
+      e = fmaf(v.w, c[4 * j + 3], e);
+      e = fmaf(v.z, c[4 * j + 2], e);
+      e = fmaf(v.y, c[4 * j + 1], e);
+      e = fmaf(v.x, c[4 * j], e);
+    }
+    return e;
+  }
+};
+
+template <bool kLinear, class Src>
+__device__ inline float log2p32(const Term32& q, int m, float2 cab, const Src& src) {
   const float e3 = fmaf(q.t3, cab.y, cab.x);
   if (kLinear) return e3;
-  const unsigned row = (unsigned)m * (unsigned)n * (unsigned)sizeof(float2);
-  const float2 l1 = tab32_at(tab, q.o1, row), l2 = tab32_at(tab, q.o2, row);
-  return fmaf(q.t1, l1.y, l1.x) + fmaf(q.t2, l2.y, l2.x) + e3;
+  return src.e12(q, m) + e3;
 }
 
 // Column pair of step m for this node: the f3 term uses one of the two segments (fixed per node).
@@ -496,9 +537,9 @@ __device__ inline float2 col_pair(const Term32& q, const Col4* __restrict__ col,
   return reinterpret_cast<const float2*>(col + m)[q.up3 ? 1 : 0];
 }
 
-template <bool kLinear, int kTier>
+template <bool kLinear, int kTier, class Src>
 __device__ inline float2 term32(const Term32& q, int m, const StepLds* __restrict__ st, const Col4* __restrict__ col,
-                                const Tab32& tab, int n) {
+                                const Src& src) {
   const StepLds sv = st[m];
   const float2 cab = col_pair(q, col, m);
   float fr;
@@ -518,7 +559,7 @@ __device__ inline float2 term32(const Term32& q, int m, const StepLds* __restric
     const float as = __builtin_amdgcn_sinf(hh - rintf(hh)) * q.inv_piphr;
     amp0 = u2 < 0.25f ? amp0 : as;
   }
-  const float amp = __builtin_amdgcn_exp2f(log2p32<kLinear>(q, m, cab, tab, n)) * amp0;
+  const float amp = __builtin_amdgcn_exp2f(log2p32<kLinear>(q, m, cab, src)) * amp0;
   return make_float2(amp * cs, amp * sn);
 }
 
@@ -535,13 +576,13 @@ __device__ inline float2 lower_edge_phasor32(double phr, const StepLds* __restri
 
 // Step m in edge form, as 2 pi phr times its term: p_m (E_(m+1) - E_m) / j.  e holds E_m on
 // entry and E_(m+1) on return.
-template <bool kLinear>
+template <bool kLinear, class Src>
 __device__ inline float2 term32_edge(const Term32& q, int m, const StepLds* __restrict__ st,
-                                     const Col4* __restrict__ col, const Tab32& tab, int n, float2& e) {
+                                     const Col4* __restrict__ col, const Src& src, float2& e) {
   const double zu = st[m].zu;
   const float2 cab = col_pair(q, col, m);
   const float2 e1 = edge_phasor32(q.phr, zu);
-  const float p = __builtin_amdgcn_exp2f(log2p32<kLinear>(q, m, cab, tab, n));
+  const float p = __builtin_amdgcn_exp2f(log2p32<kLinear>(q, m, cab, src));
   const float2 r = make_float2(p * (e1.y - e.y), p * (e.x - e1.x));
   e = e1;
   return r;
@@ -597,13 +638,13 @@ __device__ inline Split32 wave_split(bool active, const Term32& q, const StepLds
 }
 
 // Sum of the step terms over [m0, m1) in form kTier (not the edge form).
-template <bool kLinear, int kTier, int kUnroll>
+template <bool kLinear, int kTier, int kUnroll, class Src>
 __device__ inline void accumulate_range32(const Term32& q, const StepLds* __restrict__ st, const Col4* __restrict__ col,
-                                          const Tab32& tab, int n, int m0, int m1, float* a, float* b) {
+                                          const Src& src, int m0, int m1, float* a, float* b) {
   float x = 0.0f, y = 0.0f;
 #pragma unroll kUnroll
   for (int m = m0; m < m1; ++m) {
-    const float2 t = term32<kLinear, kTier>(q, m, st, col, tab, n);
+    const float2 t = term32<kLinear, kTier>(q, m, st, col, src);
     x += t.x;
     y += t.y;
   }
@@ -612,23 +653,21 @@ __device__ inline void accumulate_range32(const Term32& q, const StepLds* __rest
 }
 
 // S of one node: the wave's ranges in order, the edge range scaled by 1 / (2 pi phr) at the end.
-template <bool kLinear, int kUnroll>
+template <bool kLinear, int kUnroll, class Src>
 __device__ inline void accumulate32(const Term32& q, const Split32& sp, const StepLds* __restrict__ st,
-                                    const Col4* __restrict__ col, const Tab32& tab, int n, int M, float* sr,
-                                    float* si) {
+                                    const Col4* __restrict__ col, const Src& src, int M, float* sr, float* si) {
   float a = 0.0f, b = 0.0f;
   if (sp.small) {
-    accumulate_range32<kLinear, kTierSmall, kUnroll>(q, st, col, tab, n, 0, M, &a, &b);
+    accumulate_range32<kLinear, kTierSmall, kUnroll>(q, st, col, src, 0, M, &a, &b);
   } else {
-    if (sp.m_lo > 0) accumulate_range32<kLinear, kTierPoly, kUnroll>(q, st, col, tab, n, 0, sp.m_lo, &a, &b);
-    if (sp.m_hi > sp.m_lo)
-      accumulate_range32<kLinear, kTierMixed, kUnroll>(q, st, col, tab, n, sp.m_lo, sp.m_hi, &a, &b);
+    if (sp.m_lo > 0) accumulate_range32<kLinear, kTierPoly, kUnroll>(q, st, col, src, 0, sp.m_lo, &a, &b);
+    if (sp.m_hi > sp.m_lo) accumulate_range32<kLinear, kTierMixed, kUnroll>(q, st, col, src, sp.m_lo, sp.m_hi, &a, &b);
     if (sp.m_hi < M) {
       float2 e = lower_edge_phasor32(q.phr, st, sp.m_hi);
       float x = 0.0f, y = 0.0f;
 #pragma unroll kUnroll
       for (int m = sp.m_hi; m < M; ++m) {
-        const float2 t = term32_edge<kLinear>(q, m, st, col, tab, n, e);
+        const float2 t = term32_edge<kLinear>(q, m, st, col, src, e);
         x += t.x;
         y += t.y;
       }

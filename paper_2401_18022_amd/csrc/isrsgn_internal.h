@@ -11,6 +11,7 @@ constexpr int kMaxChannels = 1024;  // per plan (one ODE workgroup of 1024 threa
 constexpr int kMaxGridS = 1024;     // rows per part held in LDS by the tile kernels
 constexpr int kTileBlock = 256;     // threads per tile workgroup (4 wave64)
 constexpr int kTileVariants = 6;    // forward tile-kernel variants for the autotuner
+constexpr int kRank = 8;            // terms of the low-rank FP32 profile table (a multiple of 4)
 
 // Device view of one (possibly batched) channel plan.
 struct PlanView {
@@ -32,6 +33,7 @@ struct FibreParams {
   double n2, gamma_const, cr, aeff_ref, cutoff;
   int profile, photon_ratio, n_steps, grid_s, grid_v, ode_sub, precision;
   int n_spans;  // identical spans: phased-array factor per node, n-fold ASE
+  int lowrank;  // 0: the FP32 ODE step terms always read the profile table (ISRSGN_LOWRANK=0)
   double s_decades;
   int n_tab;
   const double* tab_f;      // device copies of the tables
@@ -47,6 +49,14 @@ struct Work {
   float* hdz32;     // [n_batch * M] half widths in FP32
   double* ell64;    // [M * n_total] ln rho(z_m, f_c): plan b block at M * off[b], row-major [m][c]
   float2* lt32;     // same layout: (ell * log2(e)/2, next - this) for the FP32 integrand
+  // low-rank form of lt32's values (ODE profile, FP32 form): lr_a [n_batch][M][kRank] (FP32),
+  // lr_b [n_total][kRank] (b_r, next channel's b_r - b_r), lr_rank [n_batch] (terms used; -1:
+  // the tile kernels read lt32), FP64 workspace lr_res [M * n_total] and lr_b64 [n_total][kRank]
+  float* lr_a;
+  float2* lr_b;
+  int* lr_rank;
+  double* lr_res;
+  double* lr_b64;
   double* ellL;     // [n_total] ln rho(L, f_c)
   double* tiles;    // [n_tiles]
   double* pnli;     // [n_total]

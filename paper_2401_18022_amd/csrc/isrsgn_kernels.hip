@@ -165,6 +165,116 @@ __global__ void k_table32(PlanView pv, FibreParams fp, Work w) {
   }
 }
 
+// ---------------------------------------------------------------------------- low-rank table
+// The scaled ODE profile table L(m, c) = ln rho(z_m, f_c) log2(e) / 2 of a plan is close to a
+// matrix of small rank: along z every channel follows a few smooth loss and Raman-transfer
+// shapes.  Gram-Schmidt with column pivoting in FP64 (next direction: the residual column of
+// largest norm, normalised) gives L ~ sum_r a_r(m) b_r(c) with orthonormal a_r, and stops once
+// max |residual| <= kLowRankTol -- below the half-ulp of the FP32 table itself (2.4e-7 for
+// |L| in [4, 8)).  The FP32 factors are then checked at every table point with the FP32 sum
+// the tile kernels form.  A plan that needs more than kRank terms or fails the check gets
+// rank -1, and the tile kernels read the table for it.  Linear interpolation in f commutes with
+// the factorisation, so the bound also holds between channel centres.  One block per plan.
+constexpr double kLowRankTol = 2.5e-7;
+constexpr double kLowRankCheck = 1.0e-6;
+
+__device__ inline void block_max_arg(double* v, int* arg, double* rv, int* ri) {
+  // largest v over the block (ties: smallest arg), result on every thread
+  double x = *v;
+  int k = *arg;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double y = __shfl_xor(x, o, 64);
+    const int j = __shfl_xor(k, o, 64);
+    if (y > x || (y == x && j < k)) { x = y; k = j; }
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (lane == 0) { rv[wid] = x; ri[wid] = k; }
+  __syncthreads();
+  x = rv[0];
+  k = ri[0];
+  for (int q = 1; q < nw; ++q)
+    if (rv[q] > x || (rv[q] == x && ri[q] < k)) { x = rv[q]; k = ri[q]; }
+  __syncthreads();
+  *v = x;
+  *arg = k;
+}
+
+__global__ void __launch_bounds__(1024) k_lowrank(PlanView pv, FibreParams fp, Work w) {
+  extern __shared__ double lq[];  // [M] current direction a_r
+  __shared__ double rv[16];
+  __shared__ int ri[16];
+  const int b = blockIdx.x, o = pv.off[b], n = pv.off[b + 1] - o, M = fp.n_steps, tid = threadIdx.x;
+  const int nth = blockDim.x;
+  if (!fp.lowrank) {
+    if (tid == 0) w.lr_rank[b] = -1;
+    return;
+  }
+  const double* L = w.ell64 + (size_t)M * o;
+  double* R = w.lr_res + (size_t)M * o;  // residual, [m][c] like the table
+  double* B = w.lr_b64 + (size_t)kRank * o;
+  float* Aout = w.lr_a + (size_t)M * kRank * b;
+  for (int64_t q = tid; q < (int64_t)M * n; q += nth) R[q] = L[q] * kHalfLog2e;
+  for (int64_t q = tid; q < (int64_t)M * kRank; q += nth) Aout[q] = 0.0f;
+  for (int64_t q = tid; q < (int64_t)n * kRank; q += nth) B[q] = 0.0;
+  __syncthreads();
+  int rank = -1;
+  for (int r = 0; r <= kRank; ++r) {
+    double amax = 0.0, best = -1.0;
+    int bc = 0;
+    for (int c = tid; c < n; c += nth) {
+      double ss = 0.0;
+      for (int m = 0; m < M; ++m) {
+        const double v = R[(size_t)m * n + c];
+        ss = fma(v, v, ss);
+        amax = fmax(amax, fabs(v));
+      }
+      if (ss > best) { best = ss; bc = c; }
+    }
+    int dummy = 0;
+    block_max_arg(&amax, &dummy, rv, ri);
+    if (amax <= kLowRankTol) {
+      rank = r;
+      break;
+    }
+    if (r == kRank) break;
+    block_max_arg(&best, &bc, rv, ri);
+    const double inv = 1.0 / sqrt(best);
+    for (int m = tid; m < M; m += nth) lq[m] = R[(size_t)m * n + bc] * inv;
+    __syncthreads();
+    for (int c = tid; c < n; c += nth) {
+      double cf = 0.0;
+      for (int m = 0; m < M; ++m) cf = fma(lq[m], R[(size_t)m * n + c], cf);
+      for (int m = 0; m < M; ++m) R[(size_t)m * n + c] = fma(-lq[m], cf, R[(size_t)m * n + c]);
+      B[(size_t)c * kRank + r] = cf;
+    }
+    for (int m = tid; m < M; m += nth) Aout[(size_t)m * kRank + r] = (float)lq[m];
+    __syncthreads();
+  }
+  float2* Bout = w.lr_b + (size_t)kRank * o;
+  if (rank >= 0) {
+    for (int64_t q = tid; q < (int64_t)n * kRank; q += nth) {
+      const int c = (int)(q / kRank), r = (int)(q % kRank);
+      const double v = B[q], nx = c + 1 < n ? B[q + kRank] : v;
+      Bout[q] = make_float2((float)v, (float)(nx - v));
+    }
+    __syncthreads();
+    // the FP32 sum of the tile kernels at every table point
+    double worst = 0.0;
+    for (int64_t q = tid; q < (int64_t)M * n; q += nth) {
+      const int m = (int)(q / n), c = (int)(q % n);
+      float e = 0.0f;
+      for (int r = kRank - 1; r >= 0; --r) e = fmaf(Aout[(size_t)m * kRank + r], Bout[(size_t)c * kRank + r].x, e);
+      worst = fmax(worst, fabs((double)e - L[q] * kHalfLog2e));
+    }
+    int dummy = 0;
+    block_max_arg(&worst, &dummy, rv, ri);
+    if (!(worst <= kLowRankCheck)) rank = -1;
+  }
+  if (tid == 0) w.lr_rank[b] = rank;
+}
+
 // ---------------------------------------------------------------------------- pair integrals
 struct TileArgs {
   PlanView pv;
@@ -177,7 +287,8 @@ struct TileArgs {
 };
 
 __host__ __device__ inline size_t tile_lds_bytes(int nmax, int gs, int M) {
-  return sizeof(double) * (4 * (size_t)nmax + 4 * (size_t)gs + 4) + (sizeof(StepLds) + sizeof(Col4)) * (size_t)M + 16;
+  return sizeof(double) * (4 * (size_t)nmax + 4 * (size_t)gs + 4) +
+         (sizeof(StepLds) + sizeof(Col4) + sizeof(float) * kRank) * (size_t)M + 16;
 }
 
 // Forward pair-integral kernel.  Persistent: each workgroup takes tiles (b, i, k) from a
@@ -199,9 +310,10 @@ k_tiles(TileArgs A) {
   d += 4;
   StepLds* steps = reinterpret_cast<StepLds*>(d);
   Col4* col = reinterpret_cast<Col4*>(steps + M);
-  unsigned int* tile_slot = reinterpret_cast<unsigned int*>(col + M);
+  float4* lra = reinterpret_cast<float4*>(col + M);  // the plan's a_r(m) of the low-rank table
+  unsigned int* tile_slot = reinterpret_cast<unsigned int*>(lra + M * (kRank / 4));
   const PlanView& pv = A.pv;
-  int cur_b = -1;
+  int cur_b = -1, cur_lr = -1;
   for (;;) {
     if (tid == 0) *tile_slot = A.t_begin + atomicAdd(A.w.counter, 1u);
     __syncthreads();
@@ -215,6 +327,12 @@ k_tiles(TileArgs A) {
     if (b != cur_b) {
       load_channels(ch, pv, A.P, o, n);
       if (kPrec == 0) load_steps(steps, zm, dz, A.w.hdz32 + (size_t)b * M, M);
+      if (kPrec == 0 && !kLinear) {
+        cur_lr = __builtin_amdgcn_readfirstlane(A.w.lr_rank[b]);
+        const float4* src = reinterpret_cast<const float4*>(A.w.lr_a + (size_t)M * kRank * b);
+        if (cur_lr >= 0)
+          for (int q = tid; q < M * (kRank / 4); q += kTileBlock) lra[q] = src[q];
+      }
       cur_b = b;
     }
     if (kPrec == 0) load_cols<kLinear>(col, A.w.lt32 + (size_t)M * o, n, M, i, k);
@@ -237,9 +355,16 @@ k_tiles(TileArgs A) {
           if (valid) tq = term32_setup(nd, k, n);
           const Split32 sp = wave_split(valid, tq, steps, M);
           if (!valid) continue;
-          const Tab32 tab = make_tab32(A.w.lt32 + (size_t)M * o, n, M);
           float sr, si;
-          accumulate32<kLinear, kUnroll>(tq, sp, steps, col, tab, n, M, &sr, &si);
+          if (!kLinear && cur_lr >= 0) {
+            LowRank32 src;
+            src.a = lra;
+            src.setup(tq, A.w.lr_b + (size_t)kRank * o);
+            accumulate32<kLinear, kUnroll>(tq, sp, steps, col, src, M, &sr, &si);
+          } else {
+            const Gather32 src{make_tab32(A.w.lt32 + (size_t)M * o, n, M), n};
+            accumulate32<kLinear, kUnroll>(tq, sp, steps, col, src, M, &sr, &si);
+          }
           s2v = (double)sr * sr + (double)si * si;
           if (A.w.s_store)
             static_cast<float2*>(A.w.s_store)[((int64_t)(t - A.t_begin) * 3 + part) * nodes + q] = make_float2(sr, si);
@@ -370,6 +495,10 @@ hipError_t launch_profile(const PlanView& pv, const FibreParams& fp, const doubl
     const int blocks = (int)((total + 255) / 256 < 65536 ? (total + 255) / 256 : 65536);
     hipLaunchKernelGGL(k_table32, dim3(blocks), dim3(256), 0, s, pv, fp, w);
     e = hipGetLastError();
+    if (e == hipSuccess && fp.profile != 0) {
+      hipLaunchKernelGGL(k_lowrank, dim3(pv.n_batch), dim3(1024), sizeof(double) * fp.n_steps, s, pv, fp, w);
+      e = hipGetLastError();
+    }
   }
   return e;
 }
@@ -380,11 +509,11 @@ namespace {
 using TileKernel = void (*)(TileArgs);
 #define ISRSGN_TILE_VARIANTS(P, L)                                                                 \
   {k_tiles<P, L, 1, 0>, k_tiles<P, L, 2, 0>, k_tiles<P, L, 4, 0>, k_tiles<P, L, 1, 4>, k_tiles<P, L, 2, 4>, \
-   k_tiles<P, L, 4, 4>}
+   k_tiles<P, L, 4, 3>}
 const TileKernel kTileKernels[2][2][kTileVariants] = {{ISRSGN_TILE_VARIANTS(0, false), ISRSGN_TILE_VARIANTS(0, true)},
                                                      {ISRSGN_TILE_VARIANTS(1, false), ISRSGN_TILE_VARIANTS(1, true)}};
 const char* const kTileVariantNames[kTileVariants] = {"unroll1", "unroll2", "unroll4", "unroll1-w4", "unroll2-w4",
-                                                       "unroll4-w4"};
+                                                       "unroll4-w3"};
 
 TileKernel tile_kernel(const FibreParams& fp, int variant) {
   const int v = variant < 0 || variant >= kTileVariants ? 0 : variant;
@@ -402,8 +531,10 @@ size_t tile_lds(int nmax, int gs, int M) { return tile_lds_bytes(nmax, gs, M); }
 int tile_blocks_per_cu(const FibreParams& fp, int nmax, int variant) {
   int nb = 0;
   const size_t shm = tile_lds_bytes(nmax, fp.grid_s, fp.n_steps);
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(tile_kernel(fp, variant)),
-                                                              kTileBlock, shm);
+  const void* k = reinterpret_cast<const void*>(tile_kernel(fp, variant));
+  // above 64 KiB the kernel must opt in before the occupancy query counts its blocks
+  if (shm > 65536) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kTileBlock, shm);
   if (e != hipSuccess || nb < 1) nb = 1;
   return nb;
 }

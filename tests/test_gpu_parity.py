@@ -142,6 +142,42 @@ def test_ou_band_full_grid_sampled():
     assert np.all(g["snr"] > 0) and np.isfinite(g["thr"][0])
 
 
+@pytest.mark.parametrize("make", [lambda: W.config_ou(grid_s=16, grid_v=16),
+                                  lambda: W.config_batch(n_profiles=6, grid_s=12, grid_v=12, n_steps=40)])
+def test_lowrank_profile_table_matches_table_reads(make):
+    """With the ODE profile the FP32 step terms take the f1 + f2 profile values from a low-rank
+    form of the plan's table when its factorisation meets its bound; that path and the table
+    reads (ISRSGN_LOWRANK=0) give the same tiles and SNR to the FP32 tolerance and the same
+    gradient to 1e-5 of its scale."""
+    t = torch()
+    wl = make()
+    P = t.tensor(wl.plan.p_w, dtype=t.float64, device="cuda")
+    nf = t.tensor(wl.plan.nf_lin, dtype=t.float64, device="cuda")
+    res = {}
+    for mode in ("1", "0"):
+        os.environ["ISRSGN_LOWRANK"] = mode
+        try:
+            eng = B.Engine(wl.fibre, W.FP32)
+            _, _, tl = eng.eta(wl.plan, P, tiles=True)
+            wc = eng.work_counts()
+            snr, thr, g = eng.snr_grad(wl.plan, P, nf)
+            t.cuda.synchronize()
+        finally:
+            del os.environ["ISRSGN_LOWRANK"]
+        res[mode] = (tl.cpu().numpy(), snr.cpu().numpy(), g.cpu().numpy(), wc)
+    print(f"[lowrank] {wl.name}: {res['1'][3]['lowrank_plans']} of {wl.plan.n_batch} plans, "
+          f"{res['1'][3]['lowrank_terms']} terms", flush=True)
+    assert 1 <= res["1"][3]["lowrank_plans"] <= wl.plan.n_batch and 1 <= res["1"][3]["lowrank_terms"] <= 8
+    if wl.plan.n_batch == 1:
+        assert res["1"][3]["lowrank_plans"] == 1
+    assert res["0"][3]["lowrank_plans"] == 0
+    np.testing.assert_allclose(res["1"][0], res["0"][0], rtol=TOL_TILE[W.FP32], atol=0)
+    d = np.abs(10 * np.log10(res["1"][1] / res["0"][1]))
+    assert d.max() <= TOL_SNR_DB[W.FP32], d.max()
+    scale = np.abs(res["0"][2]).max()
+    assert np.abs(res["1"][2] - res["0"][2]).max() <= 1e-5 * scale
+
+
 def test_deterministic_repeat():
     wl = W.config_cl(grid_s=32, grid_v=32, n_steps=40)
     a, b = gpu_forward(wl, W.FP32), gpu_forward(wl, W.FP32)
