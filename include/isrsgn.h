@@ -81,7 +81,11 @@ typedef struct {
   int grid_s, grid_v;       /* nodes per part: grid_s (2..1024) rows x grid_v (2..65536) per row */
   double s_decades;         /* depth of the ln|xy| window below sup|xy|, > 0 (14 is ample) */
   int ode_sub;              /* ODE: RK4 sub-steps per half distance step, 1..64 */
-  int precision;            /* ISRSGN_FP32 (FP32 integrand, FP64 phase and sums) or ISRSGN_FP64 */
+  int precision;            /* ISRSGN_FP32 (FP32 integrand, FP64 phase and sums) or ISRSGN_FP64.
+                               With the ODE profile the FP32 forward takes ln rho(z_m, f) from a
+                               low-rank form of the profile table, checked per call to stay within
+                               1e-6 of the FP64 table at every entry (else the table is read);
+                               ISRSGN_LOWRANK=0 in the environment at setup always reads the table */
   int n_spans;              /* identical spans, each followed by an amplifier restoring the launch
                              * power (App. A, eq. gain summed over spans), 1..100000: every node's
                              * |S|^2 carries the phased-array factor sin^2(n phi L/2)/sin^2(phi L/2)
