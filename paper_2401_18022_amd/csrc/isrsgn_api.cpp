@@ -221,7 +221,7 @@ int get_plan(isrsgn_fibre* h, const isrsgn_plan* p, hipStream_t s, PlanEntry** o
     if (n > nmax) nmax = n;
   }
   if (ntiles >= (int64_t)1 << 31) return fail(ISRSGN_EINVAL, "more than 2^31 tiles in one call");
-  if (tile_lds(nmax, h->desc.grid_s, h->desc.n_steps) > h->lds_max)
+  if (tile_lds(h->fp, nmax) > h->lds_max)
     return fail(ISRSGN_EINVAL, "a plan of %d channels with grid_s %d and %d steps exceeds the %zu B workgroup LDS",
                 nmax, h->desc.grid_s, h->desc.n_steps, h->lds_max);
   const int total = p->ch_offsets[p->n_batch];
@@ -354,7 +354,9 @@ int pick_variant(isrsgn_fibre* h, PlanEntry* e, const double* P, const Work& w, 
     for (auto& kv : g_tuned)
       if (kv.first == key) { *out = kv.second; return ISRSGN_OK; }
   }
-  const int64_t trial = std::min<int64_t>(e->n_tiles, std::max<int64_t>(64, 8 * (int64_t)h->n_cu));
+  // enough tiles that every workgroup of the persistent grid takes a dozen or more: with only a
+  // few each, the tail of the launch dominates and the ranking differs from the full pass
+  const int64_t trial = std::min<int64_t>(e->n_tiles, std::max<int64_t>(64, 48 * (int64_t)h->n_cu));
   const unsigned int begin = (unsigned int)((e->n_tiles - trial) / 2), end = begin + (unsigned int)trial;
   hipEvent_t a, b;
   hipError_t err;

@@ -108,7 +108,7 @@ hipError_t launch_adjoint_tiles(const PlanView& pv, const FibreParams& fp, const
 hipError_t launch_grad_finish(const PlanView& pv, const FibreParams& fp, const double* P, const Work& w,
                               double* coef, double* dthr, hipStream_t s);
 size_t adjoint_lds(int nmax, int gs, int M, int prec);
-size_t tile_lds(int nmax, int gs, int M);
+size_t tile_lds(const FibreParams& fp, int nmax);
 int adjoint_blocks_per_cu(const FibreParams& fp, int nmax, bool stored);
 int tile_blocks_per_cu(const FibreParams& fp, int nmax, int variant);
 hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);

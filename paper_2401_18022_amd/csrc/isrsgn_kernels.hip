@@ -286,10 +286,13 @@ struct TileArgs {
   unsigned int t_end;
 };
 
-__host__ __device__ inline size_t tile_lds_bytes(int nmax, int gs, int M) {
+// lowrank: room for the plan's a_r(m) rows (FP32 form with the ODE profile only)
+__host__ __device__ inline size_t tile_lds_bytes(int nmax, int gs, int M, bool lowrank) {
   return sizeof(double) * (4 * (size_t)nmax + 4 * (size_t)gs + 4) +
-         (sizeof(StepLds) + sizeof(Col4) + sizeof(float) * kRank) * (size_t)M + 16;
+         (sizeof(StepLds) + sizeof(Col4) + (lowrank ? sizeof(float) * kRank : 0)) * (size_t)M + 16;
 }
+
+__host__ __device__ inline bool tile_lowrank(const FibreParams& fp) { return fp.precision == 0 && fp.profile != 0; }
 
 // Forward pair-integral kernel.  Persistent: each workgroup takes tiles (b, i, k) from a
 // work counter; per tile it lays out the rows of each part in LDS, then strides the
@@ -311,7 +314,7 @@ k_tiles(TileArgs A) {
   StepLds* steps = reinterpret_cast<StepLds*>(d);
   Col4* col = reinterpret_cast<Col4*>(steps + M);
   float4* lra = reinterpret_cast<float4*>(col + M);  // the plan's a_r(m) of the low-rank table
-  unsigned int* tile_slot = reinterpret_cast<unsigned int*>(lra + M * (kRank / 4));
+  unsigned int* tile_slot = reinterpret_cast<unsigned int*>(kPrec == 0 && !kLinear ? lra + M * (kRank / 4) : lra);
   const PlanView& pv = A.pv;
   int cur_b = -1, cur_lr = -1;
   for (;;) {
@@ -526,11 +529,11 @@ const char* tile_variant_name(int variant) {
   return variant >= 0 && variant < kTileVariants ? kTileVariantNames[variant] : "?";
 }
 
-size_t tile_lds(int nmax, int gs, int M) { return tile_lds_bytes(nmax, gs, M); }
+size_t tile_lds(const FibreParams& fp, int nmax) { return tile_lds_bytes(nmax, fp.grid_s, fp.n_steps, tile_lowrank(fp)); }
 
 int tile_blocks_per_cu(const FibreParams& fp, int nmax, int variant) {
   int nb = 0;
-  const size_t shm = tile_lds_bytes(nmax, fp.grid_s, fp.n_steps);
+  const size_t shm = tile_lds_bytes(nmax, fp.grid_s, fp.n_steps, tile_lowrank(fp));
   const void* k = reinterpret_cast<const void*>(tile_kernel(fp, variant));
   // above 64 KiB the kernel must opt in before the occupancy query counts its blocks
   if (shm > 65536) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
@@ -544,7 +547,7 @@ hipError_t launch_tiles(const PlanView& pv, const FibreParams& fp, const double*
                         hipStream_t s) {
   hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, w.counter, reset_nodes ? w.nodes : nullptr);
   TileArgs a{pv, fp, P, w, nmax, t_begin, t_end};
-  const size_t shm = tile_lds_bytes(nmax, fp.grid_s, fp.n_steps);
+  const size_t shm = tile_lds_bytes(nmax, fp.grid_s, fp.n_steps, tile_lowrank(fp));
   const void* k = reinterpret_cast<const void*>(tile_kernel(fp, variant));
   if (shm > 65536) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   void* args[] = {&a};
