@@ -69,6 +69,16 @@ def test_several_spans_gradient_matches_duals(prec):
     check_against_duals(wl, prec, dirs)
 
 
+@pytest.mark.parametrize("prec", [W.FP64, W.FP32])
+@pytest.mark.parametrize("n_ch,seed", [(1, 7), (2, 8)])
+def test_few_channel_ode_gradient_matches_duals(prec, n_ch, seed):
+    """One and two channels with the ODE profile: single-column profile tables (the FP32 form's
+    low-rank table has one or two terms) and the ODE adjoint at its smallest size."""
+    wl = W.random_small(n_ch, seed=seed, grid_s=16, grid_v=16, n_steps=20)
+    wl = wl.with_plan(wl.plan.with_power(wl.plan.p_w * 30))
+    check_against_duals(wl, prec, [np.eye(n_ch)[c] * wl.plan.p_w[c] for c in range(n_ch)])
+
+
 def test_gradient_with_guard_channels_and_transceiver():
     wl = W.random_small(8, seed=12, grid_s=16, grid_v=16, n_steps=16)
     p = wl.plan.p_w * 20

@@ -80,7 +80,9 @@ def test_profile_matches_oracle(prec):
     lambda: W.random_small(7, seed=5, profile=W.PROFILE_CLOSED_FORM, grid_s=24, grid_v=40, n_steps=30),
     lambda: W.single_channel(grid_s=64, grid_v=64),                            # SCI only
     lambda: W.two_channel(0.2e12, grid_s=48, grid_v=16, n_steps=50),           # grid_v below one wave
-], ids=["tiny", "ragged-ode", "ragged-cf", "single", "two-ch"])
+    lambda: W.random_small(1, seed=7),                                         # one channel, ODE
+    lambda: W.random_small(2, seed=8),                                         # two channels, ODE
+], ids=["tiny", "ragged-ode", "ragged-cf", "single", "two-ch", "single-ode", "two-ode"])
 def test_all_tiles_match_oracle(make, prec):
     check(make(), prec)
 
