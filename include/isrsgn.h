@@ -85,7 +85,8 @@ typedef struct {
                                With the ODE profile the FP32 forward takes ln rho(z_m, f) from a
                                low-rank form of the profile table, checked per call to stay within
                                1e-6 of the FP64 table at every entry (else the table is read);
-                               ISRSGN_LOWRANK=0 in the environment at setup always reads the table */
+                               ISRSGN_LOWRANK=N in the environment at setup caps the terms at N
+                               (at most 8; 0 always reads the table) */
   int n_spans;              /* identical spans, each followed by an amplifier restoring the launch
                              * power (App. A, eq. gain summed over spans), 1..100000: every node's
                              * |S|^2 carries the phased-array factor sin^2(n phi L/2)/sin^2(phi L/2)

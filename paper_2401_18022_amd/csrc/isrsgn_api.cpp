@@ -690,7 +690,8 @@ int isrsgn_setup_fibre(const isrsgn_fibre_desc* d, isrsgn_fibre** out) {
   fp.n_spans = d->n_spans;
   {
     const char* lr = std::getenv("ISRSGN_LOWRANK");
-    fp.lowrank = lr && *lr == '0' ? 0 : 1;
+    const int cap = lr && *lr ? std::atoi(lr) : kRank;
+    fp.lowrank = cap < 0 ? 0 : (cap > kRank ? kRank : cap);
   }
   fp.s_decades = d->s_decades;
   fp.n_tab = d->n_tab;

@@ -33,7 +33,7 @@ struct FibreParams {
   double n2, gamma_const, cr, aeff_ref, cutoff;
   int profile, photon_ratio, n_steps, grid_s, grid_v, ode_sub, precision;
   int n_spans;  // identical spans: phased-array factor per node, n-fold ASE
-  int lowrank;  // 0: the FP32 ODE step terms always read the profile table (ISRSGN_LOWRANK=0)
+  int lowrank;  // most terms of the low-rank profile table (kRank; ISRSGN_LOWRANK=N caps it, 0: table reads)
   double s_decades;
   int n_tab;
   const double* tab_f;      // device copies of the tables

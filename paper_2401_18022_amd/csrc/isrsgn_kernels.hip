@@ -172,9 +172,10 @@ __global__ void k_table32(PlanView pv, FibreParams fp, Work w) {
 // largest norm, normalised) gives L ~ sum_r a_r(m) b_r(c) with orthonormal a_r, and stops once
 // max |residual| <= kLowRankTol -- below the half-ulp of the FP32 table itself (2.4e-7 for
 // |L| in [4, 8)).  The FP32 factors are then checked at every table point with the FP32 sum
-// the tile kernels form.  A plan that needs more than kRank terms or fails the check gets
-// rank -1, and the tile kernels read the table for it.  Linear interpolation in f commutes with
-// the factorisation, so the bound also holds between channel centres.  One block per plan.
+// the tile kernels form.  A plan that needs more than kRank terms (or the cap ISRSGN_LOWRANK=N)
+// or fails the check gets rank -1, and the tile kernels read the table for it.  Linear
+// interpolation in f commutes with the factorisation, so the bound also holds between channel
+// centres.  One block per plan.
 constexpr double kLowRankTol = 2.5e-7;
 constexpr double kLowRankCheck = 1.0e-6;
 
@@ -220,7 +221,8 @@ __global__ void __launch_bounds__(1024) k_lowrank(PlanView pv, FibreParams fp, W
   for (int64_t q = tid; q < (int64_t)n * kRank; q += nth) B[q] = 0.0;
   __syncthreads();
   int rank = -1;
-  for (int r = 0; r <= kRank; ++r) {
+  const int most = fp.lowrank;  // terms allowed (kRank unless capped)
+  for (int r = 0; r <= most; ++r) {
     double amax = 0.0, best = -1.0;
     int bc = 0;
     for (int c = tid; c < n; c += nth) {
@@ -238,7 +240,7 @@ __global__ void __launch_bounds__(1024) k_lowrank(PlanView pv, FibreParams fp, W
       rank = r;
       break;
     }
-    if (r == kRank) break;
+    if (r == most) break;
     block_max_arg(&best, &bc, rv, ri);
     const double inv = 1.0 / sqrt(best);
     for (int m = tid; m < M; m += nth) lq[m] = R[(size_t)m * n + bc] * inv;

@@ -156,8 +156,9 @@ def test_lowrank_profile_table_matches_table_reads(make):
     P = t.tensor(wl.plan.p_w, dtype=t.float64, device="cuda")
     nf = t.tensor(wl.plan.nf_lin, dtype=t.float64, device="cuda")
     res = {}
-    for mode in ("1", "0"):
-        os.environ["ISRSGN_LOWRANK"] = mode
+    for mode in ("1", "0"):            # "1": the default (up to 8 terms); "0": table reads
+        if mode == "0":
+            os.environ["ISRSGN_LOWRANK"] = "0"
         try:
             eng = B.Engine(wl.fibre, W.FP32)
             _, _, tl = eng.eta(wl.plan, P, tiles=True)
@@ -165,7 +166,7 @@ def test_lowrank_profile_table_matches_table_reads(make):
             snr, thr, g = eng.snr_grad(wl.plan, P, nf)
             t.cuda.synchronize()
         finally:
-            del os.environ["ISRSGN_LOWRANK"]
+            os.environ.pop("ISRSGN_LOWRANK", None)
         res[mode] = (tl.cpu().numpy(), snr.cpu().numpy(), g.cpu().numpy(), wc)
     print(f"[lowrank] {wl.name}: {res['1'][3]['lowrank_plans']} of {wl.plan.n_batch} plans, "
           f"{res['1'][3]['lowrank_terms']} terms", flush=True)
@@ -178,6 +179,26 @@ def test_lowrank_profile_table_matches_table_reads(make):
     assert d.max() <= TOL_SNR_DB[W.FP32], d.max()
     scale = np.abs(res["0"][2]).max()
     assert np.abs(res["1"][2] - res["0"][2]).max() <= 1e-5 * scale
+
+
+def test_lowrank_cap_falls_back_to_table_reads():
+    """The O-to-U profile table needs 8 terms; capped at 2 (ISRSGN_LOWRANK=2) the factorisation
+    gives up and the kernel reads the table, exactly as with the low-rank form disabled."""
+    t = torch()
+    wl = W.config_ou(grid_s=8, grid_v=8, n_steps=24)
+    P = t.tensor(wl.plan.p_w, dtype=t.float64, device="cuda")
+    out = {}
+    for mode in ("2", "0"):
+        os.environ["ISRSGN_LOWRANK"] = mode
+        try:
+            eng = B.Engine(wl.fibre, W.FP32)
+            _, _, tl = eng.eta(wl.plan, P, tiles=True)
+            t.cuda.synchronize()
+            out[mode] = (tl.cpu().numpy(), eng.work_counts()["lowrank_plans"])
+        finally:
+            del os.environ["ISRSGN_LOWRANK"]
+    assert out["2"][1] == 0 and out["0"][1] == 0
+    assert np.array_equal(out["2"][0], out["0"][0])
 
 
 def test_deterministic_repeat():
