@@ -483,10 +483,11 @@ enum { kTierMixed = 0, kTierSmall = 1, kTierPoly = 2 };
 // Sources of the f1 + f2 part of log2 p_m (eq. pk) for the FP32 step terms.
 //   Gather32:  the scaled profile table, interpolated at the node's f1 and f2 segments;
 //   LowRank32: the plan's low-rank form of that table, L(m, c) ~ sum_r a_r(m) b_r(c): per node
-//              c_r = b_r(f1) + b_r(f2) (interpolated like the table -- interpolation commutes
-//              with the factorisation), per step sum_r a_r(m) c_r with a_r(m) from LDS, so the
-//              step loop does no memory gathers.
+//              c_r = b_r(f1) + b_r(f2) + b_r(f3) - b_r(f_i) (interpolated like the table --
+//              interpolation commutes with the factorisation), per step sum_r a_r(m) c_r with
+//              a_r(m) from LDS: the whole exponent, with no memory gathers and no column reads.
 struct Gather32 {
+  static constexpr bool kAllTerms = false;  // the f3, f_i terms come from the tile's columns
   Tab32 tab;
   int n;
   __device__ float e12(const Term32& q, int m) const {
@@ -497,17 +498,21 @@ struct Gather32 {
 };
 
 struct LowRank32 {
+  static constexpr bool kAllTerms = true;
   const float4* __restrict__ a;  // LDS [M][kRank / 4]: a_r(m)
   float c[kRank];
-  // b: the plan's [channel][kRank] (b_r, b_r(next channel) - b_r)
-  __device__ void setup(const Term32& q, const float2* __restrict__ b) {
+  // b: the plan's [channel][kRank] (b_r, b_r(next channel) - b_r); f3 lies in segment s3 of the
+  // tile's column pair, f_i at the centre of channel i
+  __device__ void setup(const Term32& q, const float2* __restrict__ b, int s3, int i) {
     const float4* b1 = reinterpret_cast<const float4*>(b + (size_t)(q.o1 / sizeof(float2)) * kRank);
     const float4* b2 = reinterpret_cast<const float4*>(b + (size_t)(q.o2 / sizeof(float2)) * kRank);
+    const float4* b3 = reinterpret_cast<const float4*>(b + (size_t)s3 * kRank);
+    const float4* bi = reinterpret_cast<const float4*>(b + (size_t)i * kRank);
 #pragma unroll
     for (int j = 0; j < kRank / 2; ++j) {
-      const float4 u = b1[j], v = b2[j];
-      c[2 * j] = fmaf(q.t1, u.y, u.x) + fmaf(q.t2, v.y, v.x);
-      c[2 * j + 1] = fmaf(q.t1, u.w, u.z) + fmaf(q.t2, v.w, v.z);
+      const float4 u = b1[j], v = b2[j], w = b3[j], x = bi[j];
+      c[2 * j] = (fmaf(q.t1, u.y, u.x) + fmaf(q.t2, v.y, v.x)) + (fmaf(q.t3, w.y, w.x) - x.x);
+      c[2 * j + 1] = (fmaf(q.t1, u.w, u.z) + fmaf(q.t2, v.w, v.z)) + (fmaf(q.t3, w.w, w.z) - x.z);
     }
   }
   // smallest terms first; the same order as the factorisation's FP32 check
@@ -527,6 +532,7 @@ struct LowRank32 {
 
 template <bool kLinear, class Src>
 __device__ inline float log2p32(const Term32& q, int m, float2 cab, const Src& src) {
+  if constexpr (!kLinear && Src::kAllTerms) return src.e12(q, m);
   const float e3 = fmaf(q.t3, cab.y, cab.x);
   if (kLinear) return e3;
   return src.e12(q, m) + e3;

@@ -364,7 +364,9 @@ k_tiles(TileArgs A) {
           if (!kLinear && cur_lr >= 0) {
             LowRank32 src;
             src.a = lra;
-            src.setup(tq, A.w.lr_b + (size_t)kRank * o);
+            int sa, sb;
+            col_segments(k, n, &sa, &sb);
+            src.setup(tq, A.w.lr_b + (size_t)kRank * o, tq.up3 ? sb : sa, i);
             accumulate32<kLinear, kUnroll>(tq, sp, steps, col, src, M, &sr, &si);
           } else {
             const Gather32 src{make_tab32(A.w.lt32 + (size_t)M * o, n, M), n};
