@@ -175,6 +175,19 @@ def test_segment_lbfgsb_runs_a_few_iterations():
     assert len(x) == sum(counts) and max(hist) > hist[0]
 
 
+def test_two_stage_optimisation_starts_the_fine_stage_from_the_coarse_optimum():
+    from paper_2401_18022_amd import optimise
+    wl = W.config_ou(grid_s=8, grid_v=8, n_steps=12)
+    st = optimise.two_stage(wl.fibre, wl.plan, dict(grid_s=8, grid_v=8, n_steps=12),
+                            dict(grid_s=12, grid_v=12, n_steps=16), maxiter=3)
+    assert [d["stage"] for d in st] == ["coarse", "fine"]
+    assert st[0]["throughput_tbps"][1] > st[0]["throughput_tbps"][0]
+    # the fine stage's first evaluation is the coarse optimum at the fine parameters: close to
+    # the coarse stage's best throughput
+    assert abs(st[1]["throughput_tbps"][0] / st[0]["throughput_tbps"][1] - 1) < 0.02
+    assert st[1]["throughput_tbps"][1] >= st[1]["throughput_tbps"][0]
+
+
 def test_ou_full_size_adjoint_matches_fp64_differences():
     """O-to-U at its full size and in the benchmark's launch configuration (589 ch, G=128,
     N_M=112): both adjoint gradients against central differences of the FP64 form, P_k scaled by
