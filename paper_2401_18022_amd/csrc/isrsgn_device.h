@@ -218,17 +218,6 @@ __device__ inline void load_channels(const ChanLds& ch, const PlanView& pv, cons
   }
 }
 
-// Channel whose band [f_c - R_c/2, f_c + R_c/2) holds F, or -1.
-__device__ inline int find_channel(const ChanLds& ch, int n, double F) {
-  if (F < ch.lo_edge[0]) return -1;
-  int lo = 0, hi = n;
-  while (hi - lo > 1) {
-    int mid = (lo + hi) >> 1;
-    if (ch.lo_edge[mid] <= F) lo = mid; else hi = mid;
-  }
-  return F < ch.hi_edge[lo] ? lo : -1;
-}
-
 // Interpolation segment and weight of ln rho at F, given the channel c that holds F.
 __device__ inline void segment(const ChanLds& ch, int n, int c, double F, int* seg, double* t) {
   if (n == 1) { *seg = 0; *t = 0.0; return; }
@@ -261,6 +250,8 @@ __device__ inline void decode_tile(const PlanView& pv, unsigned int t, int* b, i
 // Geometry of tile (i,k) of the current plan.
 struct TileGeo {
   double fi, xp, xn, slo, shi, wi, gk;
+  double lo0;  // lower edge of the plan's first channel
+  float cinv;  // channels per Hz of the plan's lower edges, on average (0 for one channel)
 };
 
 __device__ inline TileGeo tile_geo(const ChanLds& ch, int n, int i, int k, double f_ref) {
@@ -272,6 +263,8 @@ __device__ inline TileGeo tile_geo(const ChanLds& ch, int n, int i, int k, doubl
   g.shi = ch.hi_edge[k] - g.fi;
   g.wi = g.fi - f_ref;
   g.gk = ch.psd[k];
+  g.lo0 = ch.lo_edge[0];
+  g.cinv = n > 1 ? (float)((double)(n - 1) / (ch.lo_edge[n - 1] - g.lo0)) : 0.0f;
   return g;
 }
 
@@ -292,6 +285,8 @@ __device__ inline TileGeo uniform_geo(TileGeo g) {
   g.shi = uniform_f64(g.shi);
   g.wi = uniform_f64(g.wi);
   g.gk = uniform_f64(g.gk);
+  g.lo0 = uniform_f64(g.lo0);
+  g.cinv = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(g.cinv)));
   return g;
 }
 
@@ -314,6 +309,28 @@ __device__ inline bool layout_rows(const RowLds& rw, const TileGeo& g, int part,
     }
   }
   return true;
+}
+
+// Channel whose band [f_c - R_c/2, f_c + R_c/2) holds F, or -1.  The index is first estimated
+// from the plan's mean spacing and then walked to the last lower edge at or below F: one or two
+// LDS reads on a regular grid.  After four steps the walk gives way to a binary search, so any
+// spacing gives the same channel as the search alone.
+__device__ inline int find_channel(const ChanLds& ch, int n, double F, const TileGeo& g) {
+  if (F < g.lo0) return -1;
+  int c = (int)((float)(F - g.lo0) * g.cinv);
+  c = c < 0 ? 0 : (c > n - 1 ? n - 1 : c);
+  int steps = 0;
+  while (c > 0 && ch.lo_edge[c] > F && steps < 4) { --c; ++steps; }
+  while (c + 1 < n && ch.lo_edge[c + 1] <= F && steps < 4) { ++c; ++steps; }
+  if (steps >= 4) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (ch.lo_edge[mid] <= F) lo = mid; else hi = mid;
+    }
+    c = lo;
+  }
+  return F < ch.hi_edge[c] ? c : -1;
 }
 
 // One node of a part: offsets, channels, interpolation segments, phase rate (revolutions per m).
@@ -342,8 +359,8 @@ __device__ inline bool make_node(const ChanLds& ch, const RowLds& rw, const Tile
   double x = r * ev, y = r / ev;
   if (part == kQ3) { x = -x; y = -y; }
   else if (part == kQ4) { y = -y; }
-  const int c1 = find_channel(ch, n, g.fi + x);
-  const int c2 = find_channel(ch, n, g.fi + y);
+  const int c1 = find_channel(ch, n, g.fi + x, g);
+  const int c2 = find_channel(ch, n, g.fi + y, g);
   if (c1 < 0 || c2 < 0) return false;
   nd->w = rw.w[a];
   nd->c1 = c1;
