@@ -82,7 +82,12 @@ def test_profile_matches_oracle(prec):
     lambda: W.two_channel(0.2e12, grid_s=48, grid_v=16, n_steps=50),           # grid_v below one wave
     lambda: W.random_small(1, seed=7),                                         # one channel, ODE
     lambda: W.random_small(2, seed=8),                                         # two channels, ODE
-], ids=["tiny", "ragged-ode", "ragged-cf", "single", "two-ch", "single-ode", "two-ode"])
+    # 8 channels 50 GHz apart, then 4 spread 2 THz apart: the mean-spacing estimate of a channel
+    # index is off by up to 7, so the lookup's walk gives way to the binary search
+    lambda: W.Workload("irregular-12ch", W.cl_fibre(grid_s=16, grid_v=16, n_steps=24),
+                       W.single_plan(190e12 + np.concatenate([50e9 * np.arange(8), 2.35e12 + 2e12 * np.arange(4)]),
+                                     32e9, 1e-3, W.db_to_lin(5.0))),
+], ids=["tiny", "ragged-ode", "ragged-cf", "single", "two-ch", "single-ode", "two-ode", "irregular"])
 def test_all_tiles_match_oracle(make, prec):
     check(make(), prec)
 
