@@ -387,7 +387,7 @@ struct StepLds {
   double zm;   // step midpoint z_m
   double zu;   // upper edge z_m + dz_m / 2 (the lower edge of step 0 is z = 0)
   float hdz;   // dz_m / 2
-  float zmf;   // z_m in FP32 (small-phase tier)
+  float zmf;   // z_m in FP32 (the FP32-phase form)
   float dz;    // dz_m
   float c2;    // (2 pi dz_m / 2)^2: the sinc argument squared is phr^2 c2
 };
@@ -567,7 +567,7 @@ __device__ inline float2 term32(const Term32& q, int m, const StepLds* __restric
   const float2 cab = col_pair(q, col, m);
   float fr;
   if (kTier == kTierSmall) {
-    fr = q.phrf * sv.zmf;  // |phr z_m| < 1/4 at every step of this tier: already reduced
+    fr = q.phrf * sv.zmf;  // |phr z_m| < 1/4 at every step in this form: already reduced
   } else {
     // fract(phr z_m + 1/2) - 1/2 lies in [-1/2, 1/2): one FMA, fract and convert in FP64
     fr = (float)__builtin_amdgcn_fract(fma(q.phr, sv.zm, 0.5)) - 0.5f;
