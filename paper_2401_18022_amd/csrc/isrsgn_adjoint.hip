@@ -60,8 +60,9 @@ __global__ void k_zero_counter2(unsigned int* c) { *c = 0u; }
 //
 // Per-node metadata, struct of arrays, group g of MC nodes starting at g (MC + 1) so that the
 // groups a wave reads at once sit in distinct LDS banks:
-//   key: s1 | s2 << 16 (-1: node off the support), t1, t2, w3a, w3c (w3b = wgt - w3a - w3c), and
-//   f1, f2: 1 when the node's f1 (f2) segment is the upper of its group's two.
+//   key: s1 | s2 << 16 (-1: node off the support); (t1, t2, w3a, w3c) as one 16-byte record
+//   (w3b = wgt - w3a - w3c); f1, f2: 1 when the node's f1 (f2) segment is the upper of its
+//   group's two.
 constexpr int kMetaStride = 72;  // >= 64 + 64 / MC for MC in {8, 16}
 // Workgroup of the adjoint: four wave64.  (The kernel holds over 168 VGPRs, so 2 waves per
 // SIMD; forcing 3 with six-wave groups spills registers and ran 1.7x slower.)
@@ -166,9 +167,10 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
   real* stage = reinterpret_cast<real*>(col + M);  // [waves][MC][65] (odd row stride: no bank conflicts)
   int* meta0 = reinterpret_cast<int*>(stage + kAdjWaves * MC * 65);
   int* mkey = meta0 + wv * kMetaStride;  // this wave's metadata
-  float2* mt12 = reinterpret_cast<float2*>(meta0 + kAdjWaves * kMetaStride) + wv * kMetaStride;  // (t1, t2)
-  float2* mw3 = mt12 + kAdjWaves * kMetaStride;                                                  // (w3a, w3c)
-  float2* mff = mw3 + kAdjWaves * kMetaStride;                                                   // (f1, f2)
+  // (t1, t2, w3a, w3c): one 16-byte read per node in the re-map loops
+  float4* mtw = reinterpret_cast<float4*>(meta0 + kAdjWaves * kMetaStride) + wv * kMetaStride;
+  float2* mff = reinterpret_cast<float2*>(reinterpret_cast<float4*>(meta0 + kAdjWaves * kMetaStride) +
+                                          kAdjWaves * kMetaStride) + wv * kMetaStride;  // (f1, f2)
   unsigned int* tile_slot = reinterpret_cast<unsigned int*>(meta0 + 7 * kAdjWaves * kMetaStride);
   const PlanView& pv = A.pv;
   unsigned int* counter = A.w.counter + 2;
@@ -233,8 +235,7 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
             key = kLinear ? -1 : (nd.s1 | (nd.s2 << 16));
           }
           mkey[jm] = key;
-          mt12[jm] = valid ? make_float2((float)nd.t1, (float)nd.t2) : make_float2(0.0f, 0.0f);
-          mw3[jm] = make_float2(w3a, w3c);
+          mtw[jm] = valid ? make_float4((float)nd.t1, (float)nd.t2, w3a, w3c) : make_float4(0.0f, 0.0f, w3a, w3c);
           // Most groups of MC nodes lie in one f1 segment and one f2 segment (one run each); nearly
           // all the others in two of each.  Waves whose groups all do take branch-free re-maps.
           const int s1v = key >= 0 ? (key & 0xffff) : -1, s2v = key >= 0 ? (key >> 16) : -1;
@@ -347,14 +348,13 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
 #pragma unroll 4
               for (int it = 0; it < MC; ++it) {
                 const real qv = qrow[it];
-                const float2 w3 = mw3[jb + it];
+                const float4 tw = mtw[jb + it];
                 qs += qv;
-                x3a += qv * (real)w3.x;
-                x3c += qv * (real)w3.y;
+                x3a += qv * (real)tw.z;
+                x3c += qv * (real)tw.w;
                 if (!kLinear) {
-                  const float2 tt = mt12[jb + it];
-                  a1h += qv * (real)tt.x;
-                  a2h += qv * (real)tt.y;
+                  a1h += qv * (real)tw.x;
+                  a2h += qv * (real)tw.y;
                 }
               }
               if (!kLinear && gkey >= 0) {
@@ -368,13 +368,12 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
 #pragma unroll 4
               for (int it = 0; it < MC; ++it) {
                 const real qv = qrow[it];
-                const float2 w3 = mw3[jb + it];
-                const float2 tt = mt12[jb + it];
+                const float4 tw = mtw[jb + it];
                 const float2 ff = mff[jb + it];
                 qs += qv;
-                x3a += qv * (real)w3.x;
-                x3c += qv * (real)w3.y;
-                const real u1 = qv * (real)tt.x, u2 = qv * (real)tt.y;
+                x3a += qv * (real)tw.z;
+                x3c += qv * (real)tw.w;
+                const real u1 = qv * (real)tw.x, u2 = qv * (real)tw.y;
                 a1h += u1;
                 a2h += u2;
                 b1 += qv * (real)ff.x;
@@ -393,9 +392,9 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
               for (int it = 0; it < MC; ++it) {
                 const real qv = qrow[it];
                 qs += qv;
-                const float2 w3 = mw3[jb + it];
-                x3a += qv * (real)w3.x;
-                x3c += qv * (real)w3.y;
+                const float4 tw = mtw[jb + it];
+                x3a += qv * (real)tw.z;
+                x3c += qv * (real)tw.w;
                 if (!kLinear) {
                   const int key = mkey[jb + it];
                   if (key >= 0) {
@@ -410,11 +409,10 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
                       cur2 = s2;
                       a2 = a2h = (real)0;
                     }
-                    const float2 tt = mt12[jb + it];
                     a1 += qv;
-                    a1h += qv * (real)tt.x;
+                    a1h += qv * (real)tw.x;
                     a2 += qv;
-                    a2h += qv * (real)tt.y;
+                    a2h += qv * (real)tw.y;
                   }
                 }
               }
