@@ -67,6 +67,10 @@ constexpr int kMetaStride = 72;  // >= 64 + 64 / MC for MC in {8, 16}
 // Workgroup of the adjoint: four wave64.  (The kernel holds over 168 VGPRs, so 2 waves per
 // SIMD; forcing 3 with six-wave groups spills registers and ran 1.7x slower.)
 __host__ __device__ constexpr int adj_waves(int) { return 4; }
+// Row stride of the per-wave staging [step][node], in elements.  FP32: 68, so that a re-map
+// lane's run of node values starts on a 16-byte boundary (4 values per read); FP64: 65 (odd).
+// The node-lane writes of one step are consecutive either way.
+__host__ __device__ constexpr int stage_row(int prec) { return prec == 0 ? 68 : 65; }
 
 template <int kPrec>
 struct AdjCfg {
@@ -84,11 +88,29 @@ __host__ __device__ inline size_t adjoint_lds_bytes(int nmax, int gs, int M, int
   const size_t rb = prec == 0 ? 4 : 8;
   // (+1 double: the step tables start on a 16-byte boundary)
   return sizeof(double) * (4 * (size_t)nmax + 4 * (size_t)gs + (size_t)nmax + 6 * (size_t)M + 8 + 1) +
-         (sizeof(StepLds) + sizeof(Col4)) * (size_t)M + adj_waves(prec) * (size_t)mc * 65 * rb +
+         (sizeof(StepLds) + sizeof(Col4)) * (size_t)M + adj_waves(prec) * (size_t)mc * stage_row(prec) * rb +
          adj_waves(prec) * 7 * kMetaStride * 4 + 16;
 }
 
-// Pass 2 of the FP32 form for one chunk of MC steps: out[mm * 65] = cq Re(conj(S) term_{m0+mm}),
+constexpr int kRow32 = stage_row(0);
+
+// Four consecutive staged values of one re-map lane: one 16-byte LDS read in the FP32 form
+// (a lane's run starts on a 16-byte boundary with the 68-element rows).
+template <int kPrec, class real>
+__device__ inline void load_q4(const real* p, real* q) {
+  if constexpr (kPrec == 0) {
+    const float4 v = *reinterpret_cast<const float4*>(p);
+    q[0] = v.x;
+    q[1] = v.y;
+    q[2] = v.z;
+    q[3] = v.w;
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) q[j] = p[j];
+  }
+}
+
+// Pass 2 of the FP32 form for one chunk of MC steps: out[mm * row] = cq Re(conj(S) term_{m0+mm}),
 // each step in the form of the wave's range it falls in (zero past the last step).
 template <bool kLinear, int kTier, class Src>
 __device__ inline void stage_range32(const Term32& t, int m0, int ma, int mb, float cq, float sr, float si,
@@ -97,7 +119,7 @@ __device__ inline void stage_range32(const Term32& t, int m0, int ma, int mb, fl
 #pragma unroll 2
   for (int m = ma; m < mb; ++m) {
     const float2 a = term32<kLinear, kTier>(t, m, st, col, src);
-    out[(m - m0) * 65] = cq * fmaf(sr, a.x, si * a.y);
+    out[(m - m0) * kRow32] = cq * fmaf(sr, a.x, si * a.y);
   }
 }
 
@@ -107,7 +129,7 @@ __device__ inline void stage_chunk32(const Term32& t, bool valid, const Split32&
                                      const Src& src, float* out) {
   if (!valid) {  // one branch per chunk, not per step
 #pragma unroll
-    for (int mm = 0; mm < MC; ++mm) out[mm * 65] = 0.0f;
+    for (int mm = 0; mm < MC; ++mm) out[mm * kRow32] = 0.0f;
     return;
   }
   const int m1 = min(m0 + MC, M);
@@ -123,11 +145,11 @@ __device__ inline void stage_chunk32(const Term32& t, bool valid, const Split32&
 #pragma unroll 2
       for (int m = xe; m < m1; ++m) {
         const float2 a = term32_edge<kLinear>(t, m, st, col, src, e);
-        out[(m - m0) * 65] = c * fmaf(sr, a.x, si * a.y);
+        out[(m - m0) * kRow32] = c * fmaf(sr, a.x, si * a.y);
       }
     }
   }
-  for (int m = m1; m < m0 + MC; ++m) out[(m - m0) * 65] = 0.0f;
+  for (int m = m1; m < m0 + MC; ++m) out[(m - m0) * kRow32] = 0.0f;
 }
 
 struct AdjArgs {
@@ -164,8 +186,9 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
   d += (d - reinterpret_cast<double*>(smem_raw)) & 1;  // 16-byte boundary for the step tables
   StepLds* steps = reinterpret_cast<StepLds*>(d);
   Col4* col = reinterpret_cast<Col4*>(steps + M);
-  real* stage = reinterpret_cast<real*>(col + M);  // [waves][MC][65] (odd row stride: no bank conflicts)
-  int* meta0 = reinterpret_cast<int*>(stage + kAdjWaves * MC * 65);
+  constexpr int kRow = stage_row(kPrec);
+  real* stage = reinterpret_cast<real*>(col + M);  // [waves][MC][kRow]
+  int* meta0 = reinterpret_cast<int*>(stage + kAdjWaves * MC * kRow);
   int* mkey = meta0 + wv * kMetaStride;  // this wave's metadata
   // (t1, t2, w3a, w3c): one 16-byte read per node in the re-map loops
   float4* mtw = reinterpret_cast<float4*>(meta0 + kAdjWaves * kMetaStride) + wv * kMetaStride;
@@ -302,7 +325,7 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
           atomicAdd(&gGl[c2], base2 * p1 * g.gk);
           gk_acc += base2 * p1 * p2;
         }
-        real* my_stage = stage + (size_t)wv * MC * 65;
+        real* my_stage = stage + (size_t)wv * MC * kRow;
         // pass 2 in chunks of MC steps
         for (int m0 = 0; m0 < M; m0 += MC) {
           if (kPrec == 0) {
@@ -316,7 +339,7 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
                 const double2 a = term64<kLinear>(t64, m, zm, dz, A.w.ell64 + (size_t)M * o, n);
                 qv = (real)(cq * (sr * a.x + si * a.y));
               }
-              my_stage[mm * 65 + lane] = qv;
+              my_stage[mm * kRow + lane] = qv;
             }
           }
           __syncwarp();
@@ -325,7 +348,7 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
             const int mm = lane % MC, gr = lane / MC, m = m0 + mm;
             const bool live = m < M;
             const int jb = gr * (MC + 1);
-            const real* qrow = my_stage + mm * 65 + gr * MC;
+            const real* qrow = my_stage + mm * kRow + gr * MC;
             int cur1 = -1, cur2 = -1;
             // run sums in the form's precision (at most MC nodes each), flushed to FP64:
             // a = sum q, ah = sum q t; the segment's lower channel gets a - ah, the upper ah
@@ -345,16 +368,21 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
               if (n > 1) put(cur + 1, (double)ah);
             };
             if (wave_one_run) {
-#pragma unroll 4
-              for (int it = 0; it < MC; ++it) {
-                const real qv = qrow[it];
-                const float4 tw = mtw[jb + it];
-                qs += qv;
-                x3a += qv * (real)tw.z;
-                x3c += qv * (real)tw.w;
-                if (!kLinear) {
-                  a1h += qv * (real)tw.x;
-                  a2h += qv * (real)tw.y;
+#pragma unroll 2
+              for (int i4 = 0; i4 < MC; i4 += 4) {
+                real q4[4];
+                load_q4<kPrec>(qrow + i4, q4);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                  const real qv = q4[j];
+                  const float4 tw = mtw[jb + i4 + j];
+                  qs += qv;
+                  x3a += qv * (real)tw.z;
+                  x3c += qv * (real)tw.w;
+                  if (!kLinear) {
+                    a1h += qv * (real)tw.x;
+                    a2h += qv * (real)tw.y;
+                  }
                 }
               }
               if (!kLinear && gkey >= 0) {
@@ -365,21 +393,26 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
               // two runs at most per segment key: the upper run's sums are selected by the
               // node's 0/1 flag, the lower run's are the rest
               real b1 = 0, b1h = 0, b2 = 0, b2h = 0;
-#pragma unroll 4
-              for (int it = 0; it < MC; ++it) {
-                const real qv = qrow[it];
-                const float4 tw = mtw[jb + it];
-                const float2 ff = mff[jb + it];
-                qs += qv;
-                x3a += qv * (real)tw.z;
-                x3c += qv * (real)tw.w;
-                const real u1 = qv * (real)tw.x, u2 = qv * (real)tw.y;
-                a1h += u1;
-                a2h += u2;
-                b1 += qv * (real)ff.x;
-                b1h += u1 * (real)ff.x;
-                b2 += qv * (real)ff.y;
-                b2h += u2 * (real)ff.y;
+#pragma unroll 2
+              for (int i4 = 0; i4 < MC; i4 += 4) {
+                real q4[4];
+                load_q4<kPrec>(qrow + i4, q4);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                  const real qv = q4[j];
+                  const float4 tw = mtw[jb + i4 + j];
+                  const float2 ff = mff[jb + i4 + j];
+                  qs += qv;
+                  x3a += qv * (real)tw.z;
+                  x3c += qv * (real)tw.w;
+                  const real u1 = qv * (real)tw.x, u2 = qv * (real)tw.y;
+                  a1h += u1;
+                  a2h += u2;
+                  b1 += qv * (real)ff.x;
+                  b1h += u1 * (real)ff.x;
+                  b2 += qv * (real)ff.y;
+                  b2h += u2 * (real)ff.y;
+                }
               }
               if (g1hi >= 0) {
                 flush(g1lo, qs - b1, a1h - b1h);
