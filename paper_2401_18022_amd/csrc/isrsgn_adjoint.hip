@@ -368,22 +368,27 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
               if (n > 1) put(cur + 1, (double)ah);
             };
             if (wave_one_run) {
-#pragma unroll 2
-              for (int i4 = 0; i4 < MC; i4 += 4) {
-                real q4[4];
-                load_q4<kPrec>(qrow + i4, q4);
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                  const real qv = q4[j];
-                  const float4 tw = mtw[jb + i4 + j];
-                  qs += qv;
-                  x3a += qv * (real)tw.z;
-                  x3c += qv * (real)tw.w;
-                  if (!kLinear) {
-                    a1h += qv * (real)tw.x;
-                    a2h += qv * (real)tw.y;
-                  }
+              auto node = [&](int it, real qv) {
+                const float4 tw = mtw[jb + it];
+                qs += qv;
+                x3a += qv * (real)tw.z;
+                x3c += qv * (real)tw.w;
+                if (!kLinear) {
+                  a1h += qv * (real)tw.x;
+                  a2h += qv * (real)tw.y;
                 }
+              };
+              if constexpr (kPrec == 0) {
+#pragma unroll 2
+                for (int i4 = 0; i4 < MC; i4 += 4) {
+                  real q4[4];
+                  load_q4<kPrec>(qrow + i4, q4);
+#pragma unroll
+                  for (int j = 0; j < 4; ++j) node(i4 + j, q4[j]);
+                }
+              } else {  // (the FP64 form's registers allow no more than the plain loop)
+#pragma unroll 4
+                for (int it = 0; it < MC; ++it) node(it, qrow[it]);
               }
               if (!kLinear && gkey >= 0) {
                 flush(gkey & 0xffff, qs, a1h);
