@@ -93,7 +93,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(the pair integrals would shard by COI rows; see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
     import torch

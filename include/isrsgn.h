@@ -52,7 +52,7 @@ enum {
   ISRSGN_EINVAL = -1,      /* invalid argument (message says which) */
   ISRSGN_ENOMEM = -2,      /* device allocation failed; the handle stays usable */
   ISRSGN_EDEVICE = -3,     /* HIP runtime error (message carries the HIP error string) */
-  ISRSGN_EUNSUPPORTED = -4 /* a combination this build does not provide */
+  ISRSGN_EUNSUPPORTED = -4 /* a combination the library does not provide */
 };
 
 enum { ISRSGN_FP32 = 0, ISRSGN_FP64 = 1 };
