@@ -492,3 +492,120 @@ def test_spans_without_dispersion_add_coherently_and_ase_adds_per_span():
     s1 = O.Oracle(wl.fibre, low).forward()["snr"]
     s4 = O.Oracle(wl.fibre.replace(n_spans=4), low).forward()["snr"]
     np.testing.assert_allclose(s4, s1 / 4.0, rtol=1e-9)
+
+
+# ----------------------------------------------------------------------------- setup and profile inputs
+# Pins of the per-channel fibre inputs of the oracle (Sec. II and App. A): gamma(f), the loss
+# table per channel and the mean loss of the occupied channels, the A_eff scaling of the Raman
+# gain, and the gain cut-off.  Each compares with a value worked by hand or with an invariant of
+# the Raman equations, so an inverted ratio, a per-band instead of per-channel value or a dropped
+# cut-off branch fails.
+
+def _two_point_table(f_lo, f_hi, a_lo, a_hi, alpha_lo=None, alpha_hi=None):
+    """Fibre tables linear in f between two points, so their interpolation is exact."""
+    alpha = [ALPHA, ALPHA] if alpha_lo is None else [alpha_lo, alpha_hi]
+    return dict(tab_f_hz=np.array([f_lo, f_hi]), aeff_m2=np.array([a_lo, a_hi]), alpha_per_m=np.array(alpha))
+
+
+def test_gamma_from_n2_and_effective_area_hand_values():
+    """eq. (gamma) with lambda = c/f, worked by hand for n2 = 2.6e-20 m^2/W:
+    A_eff = 80 um^2 gives 1.317442e-3 /W/m at 1550 nm and 1.558806e-3 at 1310 nm; A_eff = 60 um^2
+    at 1310 nm gives 2.078407e-3 (the paper quotes gamma ~ 2 /W/km near the zero-dispersion
+    wavelength).  With A_eff linear in f from 100 um^2 at 1675 nm to 60 um^2 at 1260 nm, the
+    frequency midpoint (208.4555 THz, 1438.160 nm) has A_eff = 80 um^2 and gamma = 1.419894e-3."""
+    f1550, f1310 = C / 1550e-9, C / 1310e-9
+    fb = W.tiny_fibre(gamma_const_per_w_m=0.0, n2_m2_per_w=2.6e-20, aeff_m2=np.array([80e-12]))
+    plan = W.single_plan(np.array([f1310, f1550])[::-1].copy(), R, 1e-3, 1.0)
+    g = O.Oracle(fb, plan).gamma()
+    np.testing.assert_allclose(g, [1.317442e-3, 1.558806e-3], rtol=1e-6)
+    fb60 = fb.replace(aeff_m2=np.array([60e-12]))
+    assert O.Oracle(fb60, W.single_plan([f1310], R, 1e-3, 1.0)).gamma()[0] == pytest.approx(2.078407e-3, rel=1e-6)
+    fa, fz = C / 1675e-9, C / 1260e-9
+    fib = W.ou_fibre(**_two_point_table(fa, fz, 100e-12, 60e-12), gamma_const_per_w_m=0.0)
+    plan = W.single_plan(np.array([fa + 1e12, 0.5 * (fa + fz), fz - 1e12]), R, 1e-3, 1.0)
+    g = O.Oracle(fib, plan).gamma()
+    assert g[1] == pytest.approx(1.419894e-3, rel=1e-6)
+    assert g[0] < g[1] < g[2]          # gamma grows with f: larger f and smaller A_eff
+
+
+def test_nli_scales_with_gamma_from_n2():
+    """P_NLI carries gamma_i^2 of the channel's own frequency: one channel at 1550 nm with
+    n2 = 2.6e-20 and A_eff = 80 um^2 gives the eta of a constant gamma = 1.317442e-3 /W/m, and
+    at twice the area a quarter of it."""
+    wl = W.single_channel(grid_s=16, grid_v=16, n_steps=16)
+    ref = O.Oracle(wl.fibre.replace(gamma_const_per_w_m=1.317442e-3), wl.plan).forward()["eta"][0]
+    fb = wl.fibre.replace(gamma_const_per_w_m=0.0, n2_m2_per_w=2.6e-20, aeff_m2=np.array([80e-12]))
+    assert O.Oracle(fb, wl.plan).forward()["eta"][0] == pytest.approx(ref, rel=1e-6)
+    fb2 = fb.replace(aeff_m2=np.array([160e-12]))
+    assert O.Oracle(fb2, wl.plan).forward()["eta"][0] == pytest.approx(ref / 4, rel=1e-6)
+
+
+def test_per_channel_loss_and_mean_loss_of_occupied_channels():
+    """No Raman gain, the O-to-U loss table (Rayleigh, infrared and OH terms on a 50 GHz grid):
+    every channel decays with its own loss, ln rho_k(z) = -alpha_k z, with alpha_k the table
+    interpolated at its centre; the distance steps use the mean loss of the channels with P > 0
+    only (32 guard channels at P = 0 here)."""
+    wl = W.config_ou(cr_per_w_m_hz=0.0, n_steps=24)
+    fb = wl.fibre
+    p = wl.plan.p_w.copy()
+    guards = np.r_[0:16, 573:589]
+    p[guards] = 0.0
+    plan = wl.plan.with_power(p)
+    pr = O.Oracle(fb, plan).profile()
+    alpha_k = np.interp(plan.f_hz, fb.tab_f_hz, fb.alpha_per_m)
+    assert np.ptp(alpha_k) > 0.5 * alpha_k.mean()                  # the loss really varies
+    np.testing.assert_allclose(pr["ell"], -pr["zm"][:, None] * alpha_k[None, :], rtol=1e-12, atol=0)
+    np.testing.assert_allclose(pr["ell_L"], -fb.span_m * alpha_k, rtol=1e-12, atol=0)
+    occupied = alpha_k[p > 0].mean()
+    assert abs(occupied / alpha_k.mean() - 1) > 1e-3               # the guards change the mean
+    assert pr["alpha_bar"] == pytest.approx(occupied, rel=1e-13)
+    edge, _, _ = O.steps(occupied, fb.span_m, fb.n_steps)
+    np.testing.assert_allclose(pr["edge"], edge, rtol=1e-15)
+
+
+def test_raman_gain_scales_with_effective_area_at_the_channel():
+    """Uniform loss, photon-number ratio on, no cut-off, A_eff 60 -> 100 um^2 across the band:
+    with C_r,k = C_r A_ref / A_eff(f_k) the Raman terms cancel pairwise in
+    sum_k P_k(z) A_eff(f_k) / f_k (gain of the lower channel f_j - f_k times its 1/(f_k C_r,k)
+    against the higher channel's loss (f_j - f_k) f_j/f_k times 1/(f_j C_r,j)), so it decays
+    exactly as exp(-alpha z).  The inverted scaling conserves sum P_k / (f_k A_eff(f_k)) instead,
+    which here drifts by more than 1e-3."""
+    f = 190e12 + 1.3e12 * np.arange(10)
+    fb = W.cl_fibre(n_steps=20, ode_sub=8, raman_cutoff_hz=0.0, photon_ratio=1, aeff_ref_m2=80e-12,
+                    **_two_point_table(f[0], f[-1], 60e-12, 100e-12))
+    plan = W.single_plan(f, R, 50e-3 * (1 + 0.1 * np.arange(10)), 1.0)
+    pr = O.Oracle(fb, plan).profile()
+    aeff = np.interp(f, fb.tab_f_hz, fb.aeff_m2)
+    pz = plan.p_w[None, :] * np.exp(pr["ell"])
+    decay = np.exp(-ALPHA * pr["zm"])
+    right = (pz * aeff / f).sum(1) / ((plan.p_w * aeff / f).sum() * decay)
+    np.testing.assert_allclose(right, 1.0, rtol=1e-9, atol=0)
+    wrong = (pz / (f * aeff)).sum(1) / ((plan.p_w / (f * aeff)).sum() * decay)
+    assert np.max(np.abs(wrong - 1)) > 1e-3
+    assert np.ptp(pr["ell_L"]) > 1.0                                  # a strong tilt: the test bites
+
+
+def test_raman_cutoff_separates_groups_and_switches_at_the_cutoff():
+    """Triangular gain to 15 THz, zero beyond: two groups of channels 16 THz apart each evolve as
+    the group alone; a pair 0.99 x 15 THz apart exchanges power, a pair 1.01 x 15 THz apart does
+    not (both then decay as exp(-alpha z) exactly)."""
+    fb = W.cl_fibre(n_steps=16, raman_cutoff_hz=15e12, photon_ratio=1, tab_f_hz=np.array([190e12]),
+                    alpha_per_m=np.array([ALPHA]), aeff_m2=np.array([80e-12]), aeff_ref_m2=80e-12)
+    ga = 186e12 + 0.2e12 * np.arange(4)
+    gb = ga[-1] + 16e12 + 0.3e12 * np.arange(3)
+    pa, pb = 60e-3 * np.array([1.0, 1.5, 0.7, 1.2]), 80e-3 * np.array([1.0, 0.5, 1.3])
+    both = O.Oracle(fb, W.single_plan(np.r_[ga, gb], R, np.r_[pa, pb], 1.0)).profile()
+    alone_a = O.Oracle(fb, W.single_plan(ga, R, pa, 1.0)).profile()
+    alone_b = O.Oracle(fb, W.single_plan(gb, R, pb, 1.0)).profile()
+    # (equal to rounding: the mean loss of 7 equal values and of 4 may differ in the last bit)
+    np.testing.assert_allclose(both["ell"][:, :4], alone_a["ell"], rtol=1e-14, atol=0)
+    np.testing.assert_allclose(both["ell"][:, 4:], alone_b["ell"], rtol=1e-14, atol=0)
+    assert np.ptp(alone_a["ell_L"]) > 1e-3 and np.ptp(alone_b["ell_L"]) > 1e-3   # each group tilts
+    for scale, exchanges in ((0.99, True), (1.01, False)):
+        f = np.array([186e12, 186e12 + scale * 15e12])
+        pr = O.Oracle(fb, W.single_plan(f, R, 0.3, 1.0)).profile()
+        plain = -ALPHA * pr["zm"]
+        if exchanges:
+            assert pr["ell"][-1, 0] - plain[-1] > 1e-3 and pr["ell"][-1, 1] - plain[-1] < -1e-3
+        else:
+            np.testing.assert_allclose(pr["ell"], plain[:, None] * np.ones((1, 2)), rtol=1e-13)
