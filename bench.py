@@ -84,6 +84,9 @@ def parse():
     ap.add_argument("--grad", dest="grad", action="store_true", default=None)
     ap.add_argument("--no-grad", dest="grad", action="store_false")
     ap.add_argument("--workload", choices=("ou", "batch"), default="ou")
+    ap.add_argument("--fp64-calls", type=int, default=3, help="timed calls of the FP64 form (median reported)")
+    ap.add_argument("--cpu-pairs", type=int, default=48,
+                    help="interferers per seeded COI in the CPU-oracle sample (16 seeded COIs)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device to device (calibrates rocprofv3 byte counters)")
     return ap.parse_args()
@@ -145,10 +148,21 @@ def main():
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     note(f"{'SNR+gradient' if grad else 'SNR'} step, FP32 form: warmup")
-    for _ in range(args.warmup):
+    keys = ("profile", "tiles", "reduce", "adjoint_tiles", "adjoint_rest", "total")
+    eager = {k: 0.0 for k in keys}
+    for _ in range(max(1, args.warmup)):
         step(eng)
+        eager = eng.stage_times()
     torch.cuda.synchronize()
-    stages = {k: 0.0 for k in ("profile", "tiles", "reduce", "adjoint_tiles", "adjoint_rest", "total")}
+    graph = args.workload == "batch"
+    if graph:
+        # the whole call -- every plan's forward, reductions and adjoint -- is captured once and
+        # then replays as one HIP graph; its stage split comes from the eager warmup call above
+        note("graph mode: capture call")
+        eng.set_graph(True)
+        step(eng)
+        torch.cuda.synchronize()
+    stages = {k: 0.0 for k in keys}
     t0 = time.perf_counter()
     for _ in range(args.steps):
         out = step(eng)
@@ -161,6 +175,8 @@ def main():
     thr = out[1].sum().item()
     work = eng.work_counts()
     ms_step = 1e3 * elapsed / args.steps
+    if graph:   # per-kernel times of the eager call, the graph's whole-call time
+        stages = {k: eager[k] * args.steps for k in keys}
     tiles_ms = stages["tiles"] / args.steps
     node_steps = work["node_steps"]
     dominant, dom_ms, dom_slots = "pair_integral_forward", tiles_ms, SLOTS_PER_NODE_STEP
@@ -173,35 +189,64 @@ def main():
     rec = recorded_traffic(dominant, args.grid) if args.workload == "ou" else None
 
     fp64 = None
-    if not args.no_fp64 and args.workload == "ou":
+    if not args.no_fp64 and args.workload == "ou" and args.fp64_calls > 0:
         note("FP64 form: first call (autotune)")
         e64 = make(W.FP64)
         step(e64)
-        note("FP64 form: timed call")
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        step(e64)
-        s64 = e64.stage_times()
-        torch.cuda.synchronize()
-        fp64 = dict(ms_per_step=1e3 * (time.perf_counter() - t1), tiles_ms=s64["tiles"],
-                    speedup_fp32_over_fp64=(1e3 * (time.perf_counter() - t1)) / ms_step)
+        times, tiles64 = [], []
+        for q in range(args.fp64_calls):
+            t1 = time.perf_counter()
+            step(e64)
+            s64 = e64.stage_times()
+            torch.cuda.synchronize()
+            times.append(1e3 * (time.perf_counter() - t1))
+            tiles64.append(s64["tiles"])
+            note(f"FP64 form: timed call {q + 1} of {args.fp64_calls} in {times[-1]:.0f} ms")
+        med = float(np.median(times))
+        fp64 = dict(ms_per_step=med, ms_per_step_calls=times, tiles_ms=float(np.median(tiles64)),
+                    speedup_fp32_over_fp64=med / ms_step)
         e64.close()
 
     cpu = None
-    if not args.no_cpu:
+    if not args.no_cpu and args.cpu_pairs > 0:
         note("CPU oracle sample")
         from oracle import oracle as orc
         sub = wl.plan.sub(0) if wl.plan.n_batch > 1 else wl.plan
         n0 = len(sub.f_hz)
-        sample_coi = [n0 // 2]
-        o = orc.Oracle(wl.fibre, sub)
+        # the 16 seeded COIs of the gradient check, each with a seeded set of interferers: pair
+        # integrals cost about the same everywhere in the tile list, so the sample's rate stands
+        # for the whole problem (the extrapolation below says so)
+        cois = W.fd_channels(n_ch=n0)
+        rng = np.random.default_rng(6)
+        per = min(args.cpu_pairs, n0)
+        ci = np.repeat(cois, per)
+        ki = np.concatenate([np.sort(rng.choice(n0, per, replace=False)) for _ in cois])
+        nproc = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+        threads = min(16, nproc)     # the host's CPU share per GPU
+        o = orc.Oracle(wl.fibre, sub, n_threads=threads)
         tc = time.perf_counter()
-        o.forward(coi=sample_coi)
+        o.tiles(ci, ki)
         dt = time.perf_counter() - tc
-        cpu = {"value": len(sample_coi) * n0 / dt, "unit": "pair-integrals/s", "cores": o.threads, "kind": "oracle",
-               "sample": f"FP64 oracle, forward pair integrals of COI {sample_coi[0]} x all {n0} interferers "
-                         f"(G={args.grid}, N_M={wl.fibre.n_steps}), {dt:.1f} s on {o.threads} threads; "
-                         f"no profile adjoint"}
+        rate = len(ci) / dt
+        model = "?"
+        try:
+            with open("/proc/cpuinfo") as fh:
+                for line in fh:
+                    if line.startswith("model name"):
+                        model = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
+        full_pairs = int(np.sum(np.diff(np.asarray(sub.offsets)) ** 2))
+        cpu = {"value": rate, "unit": "pair-integrals/s", "cores": threads, "kind": "oracle",
+               "sample": f"FP64 oracle, forward pair integrals of the 16 seeded COIs x {per} seeded interferers "
+                         f"each ({len(ci)} tiles; G={args.grid}, N_M={wl.fibre.n_steps}) in {dt:.1f} s on "
+                         f"{threads} threads; no profile adjoint",
+               "nproc": nproc, "cpu_model": model,
+               "extrapolated_full_forward_s": full_pairs / rate,
+               "extrapolation": f"linear: all {full_pairs} pair integrals of the plan at the sample's rate "
+                                f"(the work per tile is the same on average; labelled estimate, not measured)"}
 
     what = ("SNR + adjoint gradient" if grad else "SNR (forward) only")
     if args.workload == "ou":
@@ -234,6 +279,8 @@ def main():
                      "tile_variant": work["variant"]},
         "cpu_baseline": cpu,
         "stages_ms": {k: v / args.steps for k, v in stages.items()},
+        "stages_source": "eager warmup call (the timed calls replay one HIP graph)" if graph else "timed calls",
+        "graph_mode": graph,
         "snr_wall_ms": (stages["profile"] + stages["tiles"] + stages["reduce"]) / args.steps,
         "node_steps_per_s": node_steps / (tiles_ms * 1e-3),
         "throughput_tbps": thr / 1e12,

@@ -32,11 +32,21 @@
  * Conventions: SI units everywhere (Hz, W, m, s).  All arrays are FP64.
  * Arrays named *_dev are device pointers owned by the caller (e.g. torch
  * tensors); everything else is host memory, read during the call only.
- * Work is enqueued on the given HIP stream (NULL = the default stream) and the
- * calls return without synchronising.  A handle must not be used by two host
- * threads at once.  Every call returns ISRSGN_OK or a negative error code and
- * leaves a message for isrsgn_last_error(); on error nothing is written to the
- * outputs.
+ * Work is enqueued on the given HIP stream (NULL = the default stream).  A handle
+ * must not be used by two host threads at once.  Every call returns ISRSGN_OK or a
+ * negative error code and leaves a message for isrsgn_last_error().
+ *
+ * Input rules (Sec. IV, eq. loss): launch powers P_k must be finite and >= 0, P_k = 0
+ * marking an empty (guard) channel of the set A; noise figures must be finite and >= 0.
+ * With the checks on (the default, isrsgn_set_checks) every call first runs a small
+ * validation kernel on P (and NF) and waits on the host for its verdict -- so for the
+ * stream's earlier work too -- and returns ISRSGN_EINVAL, naming the first bad index,
+ * before any output is written; the calls are otherwise asynchronous.  The wait is
+ * skipped while the stream is being captured into a graph.  With the checks off (or
+ * under capture) nothing is validated: NaN propagates into the outputs and a negative
+ * power enters the PSD products as a negative density.  Errors found on the host
+ * (arguments, plans) leave the outputs untouched; a HIP error in the middle of a call
+ * may leave them partly written.
  */
 #ifndef ISRSGN_H
 #define ISRSGN_H
@@ -81,7 +91,9 @@ typedef struct {
   int grid_s, grid_v;       /* nodes per part: grid_s (2..1024) rows x grid_v (2..65536) per row */
   double s_decades;         /* depth of the ln|xy| window below sup|xy|, > 0 (14 is ample) */
   int ode_sub;              /* ODE: RK4 sub-steps per half distance step, 1..64 */
-  int precision;            /* ISRSGN_FP32 (FP32 integrand, FP64 phase and sums) or ISRSGN_FP64.
+  int precision;            /* ISRSGN_FP32 or ISRSGN_FP64.  FP32: step terms and the step sum S of each
+                               node in FP32, the phase argument phi z_m formed and reduced in FP64,
+                               node values |S|^2 w G1 G2 G3 and every later sum in FP64.
                                With the ODE profile the FP32 forward takes ln rho(z_m, f) from a
                                low-rank form of the profile table, checked per call to stay within
                                1e-6 of the FP64 table at every entry (else the table is read);
@@ -175,7 +187,13 @@ int isrsgn_stage_times(isrsgn_fibre* h, double* ms_out, int n);
  * most terms any of them needed.  n is the capacity of out (up to 7). */
 int isrsgn_work_counts(isrsgn_fibre* h, double* out, int n);
 
-/* Frees the handle and its device memory (waits for its outstanding work).  NULL is allowed. */
+/* Input checks (default on): see "Input rules" above.  Off: no validation kernel and no host
+ * wait, for callers that guarantee valid inputs (serving loops, graph capture). */
+int isrsgn_set_checks(isrsgn_fibre* h, int enabled);
+
+/* Frees the handle and its device memory.  Waits for the last call on every stream the handle
+ * was given (not for unrelated work; the runtime's own free may still wait for the device).
+ * NULL is allowed. */
 void isrsgn_destroy(isrsgn_fibre* h);
 
 /* Message of the last failed call on this thread ("" if none). Valid until the next call. */

@@ -665,6 +665,23 @@ int orc_forward(const orc_problem* pb, int n_coi, const int* coi, double* tiles,
                               thr, nullptr, nullptr, nullptr);
 }
 
+// tile(i,k) of eq. (gain_fin) (without 16/27 gamma^2 R_i) for a list of (COI, interferer) pairs.
+int orc_tiles(const orc_problem* pb, int n_pairs, const int* coi, const int* intf, double* out) {
+  if (!valid(pb)) return -1;
+  for (int q = 0; q < n_pairs; ++q)
+    if (coi[q] < 0 || coi[q] >= pb->n_ch || intf[q] < 0 || intf[q] >= pb->n_ch) return -1;
+  Model md;
+  md.pb = pb;
+  md.ch = make_channels(*pb);
+  md.st = make_steps(mean_loss(md.ch, pb->p_w), pb->span_m, pb->n_steps);
+  std::vector<double> P = powers<double>(*pb);
+  std::vector<double> G(pb->n_ch);
+  for (int c = 0; c < pb->n_ch; ++c) G[c] = P[c] / md.ch.R[c];  // rectangular PSD
+  Profile<double> pr = make_profile(*pb, md.ch, P, md.st);
+  parallel_for(n_pairs, n_workers(*pb), [&](int q) { out[q] = tile_integral(md, pr, G, coi[q], intf[q]); });
+  return 0;
+}
+
 // Same, in forward-mode dual numbers along pb->dp: values and directional derivatives.
 int orc_forward_dual(const orc_problem* pb, int n_coi, const int* coi, double* tiles, double* dtiles,
                      double* pnli, double* dpnli, double* snr, double* dsnr, double* thr, double* dthr) {

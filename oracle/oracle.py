@@ -62,6 +62,7 @@ def lib():
         L.orc_lnrho.argtypes = [P, C.c_int, _ip, _dp, _dp]
         L.orc_forward.argtypes = [P, C.c_int, _ip, _dp, _dp, _dp, _dp, _dp]
         L.orc_forward_dual.argtypes = [P, C.c_int, _ip] + [_dp] * 8
+        L.orc_tiles.argtypes = [P, C.c_int, _ip, _ip, _dp]
         L.orc_psi.argtypes = [P, C.c_int, C.c_int, _dp, _dp, _dp]
         L.orc_paper_quadrants.argtypes = [P, C.c_int, _dp]
         L.orc_gamma.argtypes = [P, _dp]
@@ -168,6 +169,16 @@ class Oracle:
         assert rc == 0
         return dict(coi=coi, tiles=tiles, dtiles=dtiles, pnli=pnli, dpnli=dpnli, snr=snr, dsnr=dsnr,
                     thr=thr.value, dthr=dthr.value)
+
+    def tiles(self, coi: Sequence[int], intf: Sequence[int]) -> np.ndarray:
+        """tile(coi[q], intf[q]) for a list of pairs (the rows of forward() restricted to those pairs)."""
+        ci = np.ascontiguousarray(np.asarray(coi, dtype=np.int32))
+        ki = np.ascontiguousarray(np.asarray(intf, dtype=np.int32))
+        assert ci.shape == ki.shape
+        out = np.zeros(len(ci))
+        rc = lib().orc_tiles(C.byref(self.pb), len(ci), ci.ctypes.data_as(_ip), ki.ctypes.data_as(_ip), _ptr(out))
+        assert rc == 0, "oracle rejected the problem or a pair"
+        return out
 
     def psi(self, i: int, x, y) -> np.ndarray:
         x, y = _arr(x), _arr(y)

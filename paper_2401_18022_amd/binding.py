@@ -22,7 +22,7 @@ ISRSGN_OK, ISRSGN_EINVAL, ISRSGN_ENOMEM, ISRSGN_EDEVICE, ISRSGN_EUNSUPPORTED = 0
 ERRORS = {ISRSGN_EINVAL: "EINVAL", ISRSGN_ENOMEM: "ENOMEM", ISRSGN_EDEVICE: "EDEVICE",
           ISRSGN_EUNSUPPORTED: "EUNSUPPORTED"}
 SYMBOLS = ["isrsgn_setup_fibre", "isrsgn_eta", "isrsgn_snr", "isrsgn_snr_grad", "isrsgn_profile",
-           "isrsgn_set_graph", "isrsgn_set_timing", "isrsgn_stage_times", "isrsgn_work_counts",
+           "isrsgn_set_graph", "isrsgn_set_checks", "isrsgn_set_timing", "isrsgn_stage_times", "isrsgn_work_counts",
            "isrsgn_destroy", "isrsgn_last_error"]
 
 _dp = C.POINTER(C.c_double)
@@ -71,6 +71,7 @@ def lib():
         L.isrsgn_profile.argtypes = [vp, C.POINTER(PlanDesc), vp, vp, vp, vp, vp, vp]
         L.isrsgn_set_timing.argtypes = [vp, C.c_int]
         L.isrsgn_set_graph.argtypes = [vp, C.c_int]
+        L.isrsgn_set_checks.argtypes = [vp, C.c_int]
         L.isrsgn_stage_times.argtypes = [vp, _dp, C.c_int]
         L.isrsgn_work_counts.argtypes = [vp, _dp, C.c_int]
         L.isrsgn_destroy.argtypes = [vp]
@@ -225,6 +226,9 @@ class Engine:
 
     def set_graph(self, on: bool = True):
         _check(lib().isrsgn_set_graph(self.h, int(on)))
+
+    def set_checks(self, on: bool = True):
+        _check(lib().isrsgn_set_checks(self.h, int(on)))
 
     def set_timing(self, on: bool = True):
         _check(lib().isrsgn_set_timing(self.h, int(on)))

@@ -157,6 +157,12 @@ struct isrsgn_fibre {
   int device = 0, n_cu = 0;
   size_t lds_max = 65536;  // LDS one workgroup may allocate on this device
   std::vector<std::unique_ptr<PlanEntry>> plans;  // most recent first
+  // input checks (isrsgn_set_checks): a validation kernel's verdict copied to pinned host memory
+  bool checks = true;
+  DevBuf d_check;
+  int* h_check = nullptr;
+  // an event recorded at the end of every call, one per stream used: isrsgn_destroy waits on these
+  std::vector<std::pair<hipStream_t, hipEvent_t>> done;
   // timing (isrsgn_set_timing): events recorded by the last call and the stage spans between them
   bool timing = false;
   std::vector<hipEvent_t> evs;
@@ -516,7 +522,8 @@ int enqueue_grad_stored(isrsgn_fibre* h, PlanEntry* e, const double* P, const do
     first = false;
     const int ma = mark(h, s);
     add_span(h, 1, mk, ma);
-    err = launch_reduce_rows(pv, h->fp, P, nf, snr_trx, w, nullptr, nullptr, snr, bt.g0, bt.g1, s);
+    // the SNR goes to the workspace (w.snr) and reaches the caller after the last batch
+    err = launch_reduce_rows(pv, h->fp, P, nf, snr_trx, w, nullptr, nullptr, nullptr, bt.g0, bt.g1, s);
     if (err == hipSuccess) err = launch_grad_rows(pv, h->fp, P, nf, snr_trx, w, bt.g0, bt.g1, s);
     if (err != hipSuccess) return hip_fail(err, "reduction");
     const int mb = mark(h, s);
@@ -529,6 +536,7 @@ int enqueue_grad_stored(isrsgn_fibre* h, PlanEntry* e, const double* P, const do
     add_span(h, 3, mb, mk);
   }
   if ((err = launch_throughput(pv, P, w, thr, s)) != hipSuccess) return hip_fail(err, "throughput");
+  if ((err = launch_copy(snr, w.snr, pv.n_total, s)) != hipSuccess) return hip_fail(err, "snr");
   if ((err = launch_grad_finish(pv, h->fp, P, w, e->coef.as<double>(), dthr, s)) != hipSuccess)
     return hip_fail(err, "adjoint");
   add_span(h, 4, mk, mark(h, s));
@@ -635,15 +643,55 @@ int run_graph(isrsgn_fibre* h, PlanEntry* e, int kind, const double* P, const do
   return ISRSGN_OK;
 }
 
+// The boundary's input rules: every launch power finite and >= 0 (P = 0 marks an empty channel)
+// and every noise figure, when given, finite and >= 0.  A one-block kernel counts the violations
+// and the host waits for its verdict (the stream's earlier work included), so a rejected call
+// writes no output.  Skipped while the stream is being captured into a graph, where a host wait
+// is not allowed, and when the caller has switched the checks off.
+int check_inputs(isrsgn_fibre* h, const double* P, const double* nf, int n, hipStream_t s) {
+  if (!h->checks) return ISRSGN_OK;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return ISRSGN_OK;
+  hipError_t err = launch_check_inputs(P, nf, n, h->d_check.as<int>(), s);
+  if (err == hipSuccess) err = hipMemcpyAsync(h->h_check, h->d_check.p, 3 * sizeof(int), hipMemcpyDeviceToHost, s);
+  if (err == hipSuccess) err = hipStreamSynchronize(s);
+  if (err != hipSuccess) return hip_fail(err, "input check");
+  if (h->h_check[0] == 0) return ISRSGN_OK;
+  if (h->h_check[1] < n)
+    return fail(ISRSGN_EINVAL, "P_w_dev[%d] is negative or not finite (launch powers must be finite and >= 0)",
+                h->h_check[1]);
+  return fail(ISRSGN_EINVAL, "nf_lin_dev[%d] is negative or not finite (noise figures must be finite and >= 0)",
+              h->h_check[2]);
+}
+
+// Marks the end of a call on stream s (isrsgn_destroy waits for these, not for the whole device).
+int record_done(isrsgn_fibre* h, hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return ISRSGN_OK;
+  hipEvent_t ev = nullptr;
+  for (auto& d : h->done)
+    if (d.first == s) ev = d.second;
+  if (!ev) {
+    hipError_t err = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (err != hipSuccess) return hip_fail(err, "completion event");
+    h->done.emplace_back(s, ev);
+  }
+  hipError_t err = hipEventRecord(ev, s);
+  return err == hipSuccess ? ISRSGN_OK : hip_fail(err, "completion event");
+}
+
 int run_call(isrsgn_fibre* h, const isrsgn_plan* plan, int kind, const double* P, const double* nf, double snr_trx,
              double* eta, double* pnli, double* tiles, double* snr, double* thr, double* dthr, hipStream_t s) {
   PlanEntry* e;
   int rc = get_plan(h, plan, s, &e);
   if (rc) return rc;
   if (kind == kGrad && (rc = ensure_grad_workspace(h, e))) return rc;
+  if ((rc = check_inputs(h, P, nf, e->n_total, s))) return rc;
   if (h->graph && variant_known(h))
-    return run_graph(h, e, kind, P, nf, snr_trx, eta, pnli, tiles, snr, thr, dthr, s);
-  return enqueue_call(h, e, kind, P, nf, snr_trx, eta, pnli, tiles, snr, thr, dthr, s);
+    rc = run_graph(h, e, kind, P, nf, snr_trx, eta, pnli, tiles, snr, thr, dthr, s);
+  else
+    rc = enqueue_call(h, e, kind, P, nf, snr_trx, eta, pnli, tiles, snr, thr, dthr, s);
+  return rc ? rc : record_done(h, s);
 }
 
 }  // namespace
@@ -712,6 +760,9 @@ int isrsgn_setup_fibre(const isrsgn_fibre_desc* d, isrsgn_fibre** out) {
   fp.tab_f = h->d_tab_f.as<double>();
   fp.tab_alpha = h->d_tab_alpha.as<double>();
   fp.tab_aeff = h->d_tab_aeff.as<double>();
+  if (!h->d_check.ensure(4 * sizeof(int))) return fail(ISRSGN_ENOMEM, "device allocation failed for the input check");
+  if ((err = hipHostMalloc(reinterpret_cast<void**>(&h->h_check), 4 * sizeof(int), hipHostMallocDefault)) != hipSuccess)
+    return hip_fail(err, "pinned host memory for the input check");
   *out = h.release();
   return ISRSGN_OK;
 }
@@ -762,12 +813,20 @@ int isrsgn_profile(isrsgn_fibre* h, const isrsgn_plan* plan, const double* P, do
   PlanEntry* e;
   int rc = get_plan(h, plan, s, &e);
   if (rc) return rc;
+  if ((rc = check_inputs(h, P, nullptr, e->n_total, s))) return rc;
   Work w = e->work();
   PlanView pv = e->view();
   hipError_t err;
   if ((err = launch_steps(pv, h->fp, P, w, s)) != hipSuccess) return hip_fail(err, "steps");
   if ((err = launch_profile(pv, h->fp, P, w, false, s)) != hipSuccess) return hip_fail(err, "profile");
   if ((err = launch_copy_profile(pv, h->fp, w, zm, dz, ell, ellL, s)) != hipSuccess) return hip_fail(err, "copy");
+  return record_done(h, s);
+}
+
+int isrsgn_set_checks(isrsgn_fibre* h, int enabled) {
+  g_err.clear();
+  if (!h) return fail(ISRSGN_EINVAL, "handle is NULL");
+  h->checks = enabled != 0;
   return ISRSGN_OK;
 }
 
@@ -827,8 +886,13 @@ int isrsgn_work_counts(isrsgn_fibre* h, double* out, int n) {
 
 void isrsgn_destroy(isrsgn_fibre* h) {
   if (!h) return;
-  (void)hipDeviceSynchronize();
+  // wait for the handle's own work only: the last call on every stream it was given
+  for (auto& d : h->done) {
+    (void)hipEventSynchronize(d.second);
+    (void)hipEventDestroy(d.second);
+  }
   for (hipEvent_t ev : h->evs) (void)hipEventDestroy(ev);
+  if (h->h_check) (void)hipHostFree(h->h_check);
   h->plans.clear();
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   delete h;

@@ -452,6 +452,42 @@ __global__ void k_throughput(PlanView pv, const double* __restrict__ P, Work w, 
   if (threadIdx.x == 0) thr[b] = s;
 }
 
+// Input rules of the boundary: launch powers finite and >= 0, noise figures (when given)
+// finite and >= 0.  One block: out[0] invalid entries, out[1] first bad power, out[2] first bad
+// noise figure (n when none).
+__global__ void __launch_bounds__(1024) k_check_inputs(const double* __restrict__ P, const double* __restrict__ nf,
+                                                       int n, int* out) {
+  __shared__ int red[3][16];
+  int bad = 0, first_p = n, first_nf = n;
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    const double p = P[c];
+    if (!(p >= 0.0) || !(p <= 1.7976931348623157e308)) { ++bad; first_p = min(first_p, c); }
+    if (nf) {
+      const double v = nf[c];
+      if (!(v >= 0.0) || !(v <= 1.7976931348623157e308)) { ++bad; first_nf = min(first_nf, c); }
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    bad += __shfl_xor(bad, o, 64);
+    first_p = min(first_p, __shfl_xor(first_p, o, 64));
+    first_nf = min(first_nf, __shfl_xor(first_nf, o, 64));
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (lane == 0) { red[0][wid] = bad; red[1][wid] = first_p; red[2][wid] = first_nf; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < nw; ++q) {
+      bad += red[0][q];
+      first_p = min(first_p, red[1][q]);
+      first_nf = min(first_nf, red[2][q]);
+    }
+    out[0] = bad;
+    out[1] = first_p;
+    out[2] = first_nf;
+  }
+}
+
 __global__ void k_copy(double* __restrict__ dst, const double* __restrict__ src, int64_t n) {
   for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
     dst[q] = src[q];
@@ -581,6 +617,11 @@ hipError_t launch_reduce(const PlanView& pv, const FibreParams& fp, const double
   hipError_t e = launch_reduce_rows(pv, fp, P, nf, snr_trx, w, eta, pnli_out, snr_out, 0, pv.n_total, s);
   if (e != hipSuccess || !thr_out) return e;
   return launch_throughput(pv, P, w, thr_out, s);
+}
+
+hipError_t launch_check_inputs(const double* P, const double* nf, int n, int* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_inputs, dim3(1), dim3(1024), 0, s, P, nf, n, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s) {

@@ -80,6 +80,7 @@ def test_null_arguments_and_destroy_null():
     assert L.isrsgn_snr_grad(None, None, None, None, 0.0, None, None, None, None) == B.ISRSGN_EINVAL
     assert L.isrsgn_profile(None, None, None, None, None, None, None, None) == B.ISRSGN_EINVAL
     assert L.isrsgn_set_timing(None, 1) == B.ISRSGN_EINVAL
+    assert L.isrsgn_set_checks(None, 1) == B.ISRSGN_EINVAL
     assert L.isrsgn_stage_times(None, None, 0) == B.ISRSGN_EINVAL
     L.isrsgn_destroy(None)
     assert isinstance(L.isrsgn_last_error(), bytes)

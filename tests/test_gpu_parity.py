@@ -245,3 +245,55 @@ def test_allocation_failure_leaves_handle_usable():
     eta, _, _ = eng.eta(plan, P)
     t.cuda.synchronize()
     assert t.isfinite(eta).all()
+
+
+def test_invalid_powers_rejected_and_handle_usable():
+    """The boundary's input rules: a negative or NaN launch power (or noise figure) is rejected with
+    EINVAL naming its index, no output is written, and the handle keeps working; with the checks
+    switched off the values are not validated (NaN propagates)."""
+    t = torch()
+    wl = W.config_tiny(grid_s=8, grid_v=8, n_steps=8)
+    eng = B.Engine(wl.fibre)
+    plan = wl.plan
+    good = t.tensor(plan.p_w, dtype=t.float64, device="cuda")
+    nf = t.tensor(plan.nf_lin, dtype=t.float64, device="cuda")
+    pa = eng._plan(plan)
+    for bad_value, idx in ((-1e-3, 3), (float("nan"), 1), (float("inf"), 0)):
+        P = good.clone()
+        P[idx] = bad_value
+        snr = t.full((5,), 7.0, dtype=t.float64, device="cuda")
+        thr = t.full((1,), 7.0, dtype=t.float64, device="cuda")
+        g = t.full((5,), 7.0, dtype=t.float64, device="cuda")
+        for call in ("snr", "grad"):
+            if call == "snr":
+                rc = B.lib().isrsgn_snr(eng.h, B.C.byref(pa.c), B._ptr(P), B._ptr(nf), 0.0, B._ptr(snr), B._ptr(thr),
+                                        B._stream())
+            else:
+                rc = B.lib().isrsgn_snr_grad(eng.h, B.C.byref(pa.c), B._ptr(P), B._ptr(nf), 0.0, B._ptr(snr),
+                                             B._ptr(thr), B._ptr(g), B._stream())
+            assert rc == B.ISRSGN_EINVAL
+            assert f"P_w_dev[{idx}]" in B.lib().isrsgn_last_error().decode()
+        with pytest.raises(B.IsrsgnError) as e:
+            eng.eta(plan, P)
+        assert e.value.code == B.ISRSGN_EINVAL
+        with pytest.raises(B.IsrsgnError):
+            eng.profile(plan, P)
+        t.cuda.synchronize()
+        assert bool((snr == 7.0).all()) and bool((thr == 7.0).all()) and bool((g == 7.0).all())
+    bad_nf = nf.clone()
+    bad_nf[4] = -1.0
+    with pytest.raises(B.IsrsgnError) as e:
+        eng.snr(plan, good, bad_nf)
+    assert e.value.code == B.ISRSGN_EINVAL and "nf_lin_dev[4]" in str(e.value)
+    # the handle is still usable, and agrees with a fresh one
+    s1, t1, g1 = eng.snr_grad(plan, good, nf)
+    s2, t2, g2 = B.Engine(wl.fibre).snr_grad(plan, good, nf)
+    t.cuda.synchronize()
+    assert t.equal(s1, s2) and t.equal(t1, t2) and t.equal(g1, g2)
+    # checks off: not validated, NaN propagates
+    eng.set_checks(False)
+    P = good.clone()
+    P[2] = float("nan")
+    snr, thr = eng.snr(plan, P, nf)
+    t.cuda.synchronize()
+    assert bool(t.isnan(thr).all())
