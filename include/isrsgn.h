@@ -152,6 +152,30 @@ int isrsgn_snr_grad(isrsgn_fibre* h, const isrsgn_plan* plan, const double* P_w_
                     double snr_trx_lin, double* snr_dev, double* thr_bps_dev, double* dthr_dP_dev,
                     void* hip_stream);
 
+/* isrsgn_snr for callers that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same arguments, input rules and results as
+ * isrsgn_snr (a single call also accepts several plans).  It calls no allocator: the plan's device
+ * copy and the call's whole workspace (distance steps, power-profile tables, tile integrals,
+ * reductions) live in one static device array of ISRSGN_NOALLOC_SCRATCH_BYTES, of which every GPU
+ * the library runs on holds its own copy until the process ends (its address is looked up at
+ * isrsgn_setup_fibre).  The plan reaches the device in kernel arguments, not through a copy from
+ * host memory, so a captured call replays with the plan it was captured with.
+ *   Limit: the call's workspace must fit the array, else ISRSGN_EINVAL stating the need.  In bytes,
+ *   each section rounded up to 256: per plan about 8 N_b^2 (tiles) plus 8 N_ch n_steps (FP64
+ *   table), 8 N_ch n_steps more in the FP32 form and 8 N_ch n_steps more with the FP32 form and the
+ *   ODE profile, plus O(N_ch + n_batch n_steps) small arrays: 4.3 MiB for 589 channels at 112 steps,
+ *   10.8 MiB for 1024 channels.
+ *   Sharing: every call on a GPU uses that GPU's one array, which keeps the last call's contents;
+ *   calls that overlap on one GPU (several streams, handles or host threads) race and give wrong
+ *   results, so the caller serialises them.
+ * The tile-kernel variant is the autotuner's earlier choice for the discretisation (or
+ * ISRSGN_TILE_VARIANT), else a fixed default; results agree with isrsgn_snr to the precision
+ * form's rounding.  Stage timers and work counters do not cover this call, and isrsgn_destroy does
+ * not wait for it: synchronise its stream before destroying the handle. */
+#define ISRSGN_NOALLOC_SCRATCH_BYTES (32 * 1024 * 1024)
+int isrsgn_snr_noalloc(isrsgn_fibre* h, const isrsgn_plan* plan, const double* P_w_dev, const double* nf_lin_dev,
+                       double snr_trx_lin, double* snr_dev, double* thr_bps_dev, void* hip_stream);
+
 /* The distance steps and the power profile on their own (App. A, eq. pk):
  *   z_mid_dev[n_batch * n_steps], dz_dev[n_batch * n_steps]  step midpoints and widths per plan
  *   ell_dev   per plan an n_steps x N_b row-major block of ln rho(z_m, f_c)

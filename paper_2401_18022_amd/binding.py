@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(PKG, "libisrsgn.so")
 ISRSGN_OK, ISRSGN_EINVAL, ISRSGN_ENOMEM, ISRSGN_EDEVICE, ISRSGN_EUNSUPPORTED = 0, -1, -2, -3, -4
 ERRORS = {ISRSGN_EINVAL: "EINVAL", ISRSGN_ENOMEM: "ENOMEM", ISRSGN_EDEVICE: "EDEVICE",
           ISRSGN_EUNSUPPORTED: "EUNSUPPORTED"}
-SYMBOLS = ["isrsgn_setup_fibre", "isrsgn_eta", "isrsgn_snr", "isrsgn_snr_grad", "isrsgn_profile",
+SYMBOLS = ["isrsgn_setup_fibre", "isrsgn_eta", "isrsgn_snr", "isrsgn_snr_grad", "isrsgn_snr_noalloc", "isrsgn_profile",
            "isrsgn_set_graph", "isrsgn_set_checks", "isrsgn_set_timing", "isrsgn_stage_times", "isrsgn_work_counts",
            "isrsgn_destroy", "isrsgn_last_error"]
 
@@ -68,6 +68,7 @@ def lib():
         L.isrsgn_eta.argtypes = [vp, C.POINTER(PlanDesc), vp, vp, vp, vp, vp]
         L.isrsgn_snr.argtypes = [vp, C.POINTER(PlanDesc), vp, vp, C.c_double, vp, vp, vp]
         L.isrsgn_snr_grad.argtypes = [vp, C.POINTER(PlanDesc), vp, vp, C.c_double, vp, vp, vp, vp]
+        L.isrsgn_snr_noalloc.argtypes = [vp, C.POINTER(PlanDesc), vp, vp, C.c_double, vp, vp, vp]
         L.isrsgn_profile.argtypes = [vp, C.POINTER(PlanDesc), vp, vp, vp, vp, vp, vp]
         L.isrsgn_set_timing.argtypes = [vp, C.c_int]
         L.isrsgn_set_graph.argtypes = [vp, C.c_int]
@@ -210,6 +211,20 @@ class Engine:
         _check(lib().isrsgn_snr_grad(self.h, C.byref(pa.c), _ptr(P), _ptr(nf), float(snr_trx_lin), _ptr(snr),
                                      _ptr(thr), _ptr(g), _stream()))
         return snr, thr, g
+
+    def snr_noalloc(self, plan: W.Plan, P, nf, snr_trx_lin: float = 0.0, out=None):
+        """isrsgn_snr_noalloc: the SNR call on the library's static device scratch (no allocation
+        inside the library); `out` = (snr, thr) tensors to write into, else new ones."""
+        torch = _torch()
+        pa = self._plan(plan)
+        P, nf = _dev(P, pa.n_total, "P"), _dev(nf, pa.n_total, "nf")
+        if out is None:
+            out = (torch.empty(pa.n_total, dtype=torch.float64, device="cuda"),
+                   torch.empty(pa.n_batch, dtype=torch.float64, device="cuda"))
+        snr, thr = _dev(out[0], pa.n_total, "snr"), _dev(out[1], pa.n_batch, "thr")
+        _check(lib().isrsgn_snr_noalloc(self.h, C.byref(pa.c), _ptr(P), _ptr(nf), float(snr_trx_lin), _ptr(snr),
+                                        _ptr(thr), _stream()))
+        return snr, thr
 
     def profile(self, plan: W.Plan, P):
         torch = _torch()

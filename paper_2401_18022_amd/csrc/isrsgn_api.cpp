@@ -18,6 +18,12 @@
 
 using namespace isrsgn;
 
+// Device scratch of isrsgn_snr_noalloc: the plan's device copy and the whole workspace of a call
+// live here instead of memory the library allocates.  Every GPU the library runs on holds its own
+// copy until the process ends.  In host code `scratch` names a host-side stand-in: kernels get the
+// per-device address that hipGetSymbolAddress returns (scratch_address below), never the name.
+static __device__ __align__(256) unsigned char scratch[ISRSGN_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 thread_local std::string g_err;
@@ -207,8 +213,28 @@ int validate_desc(const isrsgn_fibre_desc* d) {
   return ISRSGN_OK;
 }
 
-// Validates a plan and returns its resident copy (uploading and setting it up on a miss).
-int get_plan(isrsgn_fibre* h, const isrsgn_plan* p, hipStream_t s, PlanEntry** out) {
+// Address of this device's copy of `scratch`, looked up once per device (with that device current)
+// and kept; isrsgn_setup_fibre calls it for the handle's device.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(ISRSGN_EDEVICE, "device %d is beyond the %d the library tracks", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (err != hipSuccess) return hip_fail(err, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(ISRSGN_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return ISRSGN_OK;
+}
+
+// Plan rules of include/isrsgn.h; *ntiles_out and *nmax_out get the tile count and the largest plan.
+int validate_plan(const isrsgn_fibre* h, const isrsgn_plan* p, int64_t* ntiles_out, int* nmax_out) {
   if (!p) return fail(ISRSGN_EINVAL, "plan is NULL");
   if (p->n_batch < 1 || !p->ch_offsets || !p->f_hz || !p->rs_hz) return fail(ISRSGN_EINVAL, "plan needs n_batch >= 1 and arrays");
   if (p->ch_offsets[0] != 0) return fail(ISRSGN_EINVAL, "ch_offsets[0] must be 0");
@@ -230,6 +256,16 @@ int get_plan(isrsgn_fibre* h, const isrsgn_plan* p, hipStream_t s, PlanEntry** o
   if (tile_lds(h->fp, nmax) > h->lds_max)
     return fail(ISRSGN_EINVAL, "a plan of %d channels with grid_s %d and %d steps exceeds the %zu B workgroup LDS",
                 nmax, h->desc.grid_s, h->desc.n_steps, h->lds_max);
+  *ntiles_out = ntiles;
+  *nmax_out = nmax;
+  return ISRSGN_OK;
+}
+
+// Validates a plan and returns its resident copy (uploading and setting it up on a miss).
+int get_plan(isrsgn_fibre* h, const isrsgn_plan* p, hipStream_t s, PlanEntry** out) {
+  int64_t ntiles = 0;
+  int nmax = 0;
+  if (const int rc = validate_plan(h, p, &ntiles, &nmax)) return rc;
   const int total = p->ch_offsets[p->n_batch];
   uint64_t key = 1469598103934665603ull;
   key = fnv1a(p->ch_offsets, sizeof(int) * (p->n_batch + 1), key);
@@ -308,8 +344,8 @@ void add_span(isrsgn_fibre* h, int stage, int a, int b) {
   if (a >= 0 && b >= 0) h->spans.push_back({stage, a, b});
 }
 
-int tile_grid(isrsgn_fibre* h, const PlanEntry* e, int variant, int64_t tiles) {
-  const int per_cu = tile_blocks_per_cu(h->fp, e->nmax, variant);
+int tile_grid(isrsgn_fibre* h, int nmax, int variant, int64_t tiles) {
+  const int per_cu = tile_blocks_per_cu(h->fp, nmax, variant);
   int64_t g = (int64_t)per_cu * h->n_cu;
   if (g > tiles) g = tiles;
   return (int)(g < 1 ? 1 : g);
@@ -373,7 +409,7 @@ int pick_variant(isrsgn_fibre* h, PlanEntry* e, const double* P, const Work& w, 
   for (int v = 0; v < kTileVariants && err == hipSuccess; ++v) {
     for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {
       (void)hipEventRecord(a, s);
-      err = launch_tiles(pv, h->fp, P, w, e->nmax, tile_grid(h, e, v, trial), v, begin, end, true, s);
+      err = launch_tiles(pv, h->fp, P, w, e->nmax, tile_grid(h, e->nmax, v, trial), v, begin, end, true, s);
       (void)hipEventRecord(b, s);
       if (err == hipSuccess) err = hipEventSynchronize(b);
       float ms = 0.f;
@@ -426,7 +462,7 @@ int forward(isrsgn_fibre* h, PlanEntry* e, const double* P, const double* nf, do
   const int rc = prologue(h, e, P, w, keep_states, s, &variant, &m1);
   if (rc) return rc;
   hipError_t err;
-  if ((err = launch_tiles(pv, h->fp, P, w, e->nmax, tile_grid(h, e, variant, e->n_tiles), variant, 0u,
+  if ((err = launch_tiles(pv, h->fp, P, w, e->nmax, tile_grid(h, e->nmax, variant, e->n_tiles), variant, 0u,
                           (unsigned int)e->n_tiles, true, s)) != hipSuccess)
     return hip_fail(err, "pair integrals");
   const int m2 = mark(h, s);
@@ -516,7 +552,7 @@ int enqueue_grad_stored(isrsgn_fibre* h, PlanEntry* e, const double* P, const do
   bool first = true;
   for (const auto& bt : e->batches) {
     const int64_t nt = (int64_t)bt.t1 - bt.t0;
-    if ((err = launch_tiles(pv, h->fp, P, w, e->nmax, tile_grid(h, e, variant, nt), variant, bt.t0, bt.t1, first,
+    if ((err = launch_tiles(pv, h->fp, P, w, e->nmax, tile_grid(h, e->nmax, variant, nt), variant, bt.t0, bt.t1, first,
                             s)) != hipSuccess)
       return hip_fail(err, "pair integrals");
     first = false;
@@ -694,6 +730,89 @@ int run_call(isrsgn_fibre* h, const isrsgn_plan* plan, int kind, const double* P
   return rc ? rc : record_done(h, s);
 }
 
+// ---------------------------------------------------------------------------- no allocation
+// The workspace of one isrsgn_snr_noalloc call, carved out of the scratch array from `base`
+// (256-byte aligned sections): the plan's device copy and the Work fields the forward kernels
+// use.  Returns the bytes it takes (with base = 0 it only sizes).
+size_t carve_noalloc(const isrsgn_fibre* h, int nb, int nt, int64_t ntiles, uintptr_t base, PlanView* pv, Work* w) {
+  size_t used = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = reinterpret_cast<char*>(base + used);
+    used += (bytes + 255) & ~(size_t)255;
+    return p;
+  };
+  const size_t M = (size_t)h->desc.n_steps, n = (size_t)nt, b = (size_t)nb;
+  const bool fp32 = h->desc.precision == ISRSGN_FP32, lr = fp32 && h->desc.profile == ISRSGN_PROFILE_ODE;
+  *pv = PlanView{};
+  pv->n_batch = nb;
+  pv->n_total = nt;
+  pv->n_tiles = ntiles;
+  pv->off = reinterpret_cast<int*>(take(4 * (b + 1)));
+  pv->toff = reinterpret_cast<int64_t*>(take(8 * (b + 1)));
+  pv->f = reinterpret_cast<double*>(take(8 * n));
+  pv->R = reinterpret_cast<double*>(take(8 * n));
+  pv->alpha = reinterpret_cast<double*>(take(8 * n));
+  pv->aeff = reinterpret_cast<double*>(take(8 * n));
+  pv->gamma = reinterpret_cast<double*>(take(8 * n));
+  pv->cr = reinterpret_cast<double*>(take(8 * n));
+  *w = Work{};
+  w->abar = reinterpret_cast<double*>(take(8 * b));
+  w->zm = reinterpret_cast<double*>(take(8 * b * M));
+  w->dz = reinterpret_cast<double*>(take(8 * b * M));
+  w->hdz32 = reinterpret_cast<float*>(take(4 * b * M));
+  w->ell64 = reinterpret_cast<double*>(take(8 * n * M));
+  if (fp32) w->lt32 = reinterpret_cast<float2*>(take(8 * n * M));
+  if (lr) {
+    w->lr_a = reinterpret_cast<float*>(take(4 * b * M * kRank));
+    w->lr_b = reinterpret_cast<float2*>(take(8 * n * kRank));
+    w->lr_rank = reinterpret_cast<int*>(take(4 * b));
+    w->lr_res = reinterpret_cast<double*>(take(8 * n * M));
+    w->lr_b64 = reinterpret_cast<double*>(take(8 * n * kRank));
+  }
+  w->ellL = reinterpret_cast<double*>(take(8 * n));
+  w->tiles = reinterpret_cast<double*>(take(8 * (size_t)ntiles));
+  w->pnli = reinterpret_cast<double*>(take(8 * n));
+  w->snr = reinterpret_cast<double*>(take(8 * n));
+  char* counter = take(64);
+  w->counter = reinterpret_cast<unsigned int*>(counter);
+  w->nodes = reinterpret_cast<unsigned long long*>(counter + 32);
+  return used;
+}
+
+// Host values to the device through kernel arguments: dst[q] = fill(q) for q < n (8-byte words).
+template <class Fill>
+hipError_t put_words(void* dst, int64_t n, Fill&& fill, hipStream_t s) {
+  WordChunk c;
+  for (int64_t q0 = 0; q0 < n; q0 += kChunkWords) {
+    c.n = (int)std::min<int64_t>(kChunkWords, n - q0);
+    for (int j = 0; j < c.n; ++j) c.w[j] = fill(q0 + j);
+    const hipError_t e = launch_put_words(static_cast<unsigned long long*>(dst) + q0, c, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+unsigned long long word_of(double x) {
+  unsigned long long u;
+  std::memcpy(&u, &x, sizeof(u));
+  return u;
+}
+
+// Tile-kernel variant without tuning: forced, or the autotuner's earlier choice, or a default.
+int noalloc_variant(isrsgn_fibre* h) {
+  const char* force = std::getenv("ISRSGN_TILE_VARIANT");
+  if (force && *force) {
+    const int v = std::atoi(force);
+    return v >= 0 && v < kTileVariants ? v : 0;
+  }
+  const TuneKey key{h->desc.precision, h->desc.profile, h->desc.grid_s, h->desc.grid_v, h->desc.n_steps};
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  read_tune_file();
+  for (auto& kv : g_tuned)
+    if (kv.first == key) return kv.second;
+  return h->desc.precision == ISRSGN_FP32 ? 4 : 0;  // unroll 2 at 4 waves/SIMD; FP64: unroll 1
+}
+
 }  // namespace
 
 extern "C" {
@@ -745,6 +864,10 @@ int isrsgn_setup_fibre(const isrsgn_fibre_desc* d, isrsgn_fibre** out) {
   fp.n_tab = d->n_tab;
   hipError_t err;
   if ((err = hipGetDevice(&h->device)) != hipSuccess) return hip_fail(err, "hipGetDevice");
+  {
+    void* sp = nullptr;
+    if ((rc = scratch_address(h->device, &sp))) return rc;
+  }
   int lds_max = 0;
   if ((err = hipDeviceGetAttribute(&h->n_cu, hipDeviceAttributeMultiprocessorCount, h->device)) != hipSuccess ||
       (err = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device)) != hipSuccess)
@@ -792,6 +915,65 @@ int isrsgn_snr_grad(isrsgn_fibre* h, const isrsgn_plan* plan, const double* P, c
   if (!(snr_trx >= 0) || !is_fin(snr_trx)) return fail(ISRSGN_EINVAL, "snr_trx_lin must be finite and >= 0");
   return run_call(h, plan, kGrad, P, nf, snr_trx, nullptr, nullptr, nullptr, snr, thr, dthr,
                   static_cast<hipStream_t>(stream));
+}
+
+int isrsgn_snr_noalloc(isrsgn_fibre* h, const isrsgn_plan* plan, const double* P, const double* nf, double snr_trx,
+                       double* snr, double* thr, void* stream) {
+  g_err.clear();
+  if (!h || !P || !nf || !snr || !thr) return fail(ISRSGN_EINVAL, "handle, P, NF, snr and thr pointers are required");
+  if (!(snr_trx >= 0) || !is_fin(snr_trx)) return fail(ISRSGN_EINVAL, "snr_trx_lin must be finite and >= 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int64_t ntiles = 0;
+  int nmax = 0;
+  int rc = validate_plan(h, plan, &ntiles, &nmax);
+  if (rc) return rc;
+  int dev = -1;
+  hipError_t err = hipGetDevice(&dev);
+  if (err != hipSuccess) return hip_fail(err, "hipGetDevice");
+  if (dev != h->device)
+    return fail(ISRSGN_EINVAL, "the handle was set up on device %d but device %d is current", h->device, dev);
+  void* base = nullptr;
+  if ((rc = scratch_address(dev, &base))) return rc;
+  const int nb = plan->n_batch, nt = plan->ch_offsets[nb];
+  PlanView pv;
+  Work w;
+  const size_t need = carve_noalloc(h, nb, nt, ntiles, 0, &pv, &w);
+  if (need > (size_t)ISRSGN_NOALLOC_SCRATCH_BYTES)
+    return fail(ISRSGN_EINVAL, "the plan needs %zu B of workspace; the no-allocation scratch holds %zu B (isrsgn_snr "
+                "has no such limit)", need, (size_t)ISRSGN_NOALLOC_SCRATCH_BYTES);
+  carve_noalloc(h, nb, nt, ntiles, reinterpret_cast<uintptr_t>(base), &pv, &w);
+  if ((rc = check_inputs(h, P, nf, nt, s))) return rc;
+  // the plan: offsets as pairs of ints per word, tile offsets, centres and symbol rates
+  const int* off = plan->ch_offsets;
+  err = put_words(const_cast<int*>(pv.off), (nb + 2) / 2, [&](int64_t q) {
+    const unsigned long long lo = (unsigned int)off[2 * q];
+    const unsigned long long hi = 2 * q + 1 <= nb ? (unsigned int)off[2 * q + 1] : 0u;
+    return lo | (hi << 32);
+  }, s);
+  int64_t acc = 0;
+  if (err == hipSuccess)
+    err = put_words(const_cast<int64_t*>(pv.toff), nb + 1, [&](int64_t q) {
+      const unsigned long long v = (unsigned long long)acc;
+      if (q < nb) {
+        const int64_t n = off[q + 1] - off[q];
+        acc += n * n;
+      }
+      return v;
+    }, s);
+  if (err == hipSuccess) err = put_words(const_cast<double*>(pv.f), nt, [&](int64_t q) { return word_of(plan->f_hz[q]); }, s);
+  if (err == hipSuccess)
+    err = put_words(const_cast<double*>(pv.R), nt, [&](int64_t q) { return word_of(plan->rs_hz[q]); }, s);
+  if (err != hipSuccess) return hip_fail(err, "plan upload");
+  if ((err = launch_channel_setup(pv, h->fp, s)) != hipSuccess) return hip_fail(err, "channel setup");
+  if ((err = launch_steps(pv, h->fp, P, w, s)) != hipSuccess) return hip_fail(err, "steps");
+  if ((err = launch_profile(pv, h->fp, P, w, false, s)) != hipSuccess) return hip_fail(err, "profile");
+  const int variant = noalloc_variant(h);
+  if ((err = launch_tiles(pv, h->fp, P, w, nmax, tile_grid(h, nmax, variant, ntiles), variant, 0u,
+                          (unsigned int)ntiles, true, s)) != hipSuccess)
+    return hip_fail(err, "pair integrals");
+  if ((err = launch_reduce(pv, h->fp, P, nf, snr_trx, w, nullptr, nullptr, snr, thr, s)) != hipSuccess)
+    return hip_fail(err, "reduction");
+  return ISRSGN_OK;
 }
 
 int isrsgn_set_graph(isrsgn_fibre* h, int enabled) {

@@ -112,6 +112,14 @@ size_t tile_lds(const FibreParams& fp, int nmax);
 int adjoint_blocks_per_cu(const FibreParams& fp, int nmax, bool stored);
 int tile_blocks_per_cu(const FibreParams& fp, int nmax, int variant);
 hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
+// Up to kChunkWords 8-byte words carried to the device in the kernel's arguments (no copy from
+// host memory, so a captured launch keeps its values): dst[q] = words[q] for q < n.
+constexpr int kChunkWords = 240;
+struct WordChunk {
+  unsigned long long w[kChunkWords];
+  int n;
+};
+hipError_t launch_put_words(unsigned long long* dst, const WordChunk& c, hipStream_t s);
 // out[0] invalid entries of P (finite, >= 0) and nf (when given: finite, >= 0); out[1], out[2]
 // the first bad index of each (n when none)
 hipError_t launch_check_inputs(const double* P, const double* nf, int n, int* out, hipStream_t s);

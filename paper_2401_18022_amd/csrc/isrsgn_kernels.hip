@@ -493,6 +493,11 @@ __global__ void k_copy(double* __restrict__ dst, const double* __restrict__ src,
     dst[q] = src[q];
 }
 
+__global__ void k_put_words(unsigned long long* __restrict__ dst, WordChunk c) {
+  const int q = threadIdx.x;
+  if (q < c.n) dst[q] = c.w[q];
+}
+
 __global__ void k_copy_profile(PlanView pv, FibreParams fp, Work w, double* zm, double* dz, double* ell,
                                double* ellL) {
   const int M = fp.n_steps;
@@ -627,6 +632,11 @@ hipError_t launch_check_inputs(const double* P, const double* nf, int n, int* ou
 hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s) {
   const int64_t blocks = (n + 255) / 256 < 2048 ? (n + 255) / 256 : 2048;
   hipLaunchKernelGGL(k_copy, dim3((unsigned)(blocks < 1 ? 1 : blocks)), dim3(256), 0, s, dst, src, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_put_words(unsigned long long* dst, const WordChunk& c, hipStream_t s) {
+  hipLaunchKernelGGL(k_put_words, dim3(1), dim3(256), 0, s, dst, c);
   return hipGetLastError();
 }
 
