@@ -68,8 +68,6 @@ inline Dual& operator*=(Dual& a, Dual b) { a = a * b; return a; }
 
 inline double Val(double x) { return x; }
 inline double Val(Dual x) { return x.v; }
-inline double Der(double) { return 0.0; }
-inline double Der(Dual x) { return x.d; }
 inline double Exp(double x) { return std::exp(x); }
 inline Dual Exp(Dual x) { double e = std::exp(x.v); return {e, e * x.d}; }
 inline double Log(double x) { return std::log(x); }
@@ -78,6 +76,75 @@ inline double Sinh(double x) { return std::sinh(x); }
 inline Dual Sinh(Dual x) { return {std::sinh(x.v), std::cosh(x.v) * x.d}; }
 inline double Log2(double x) { return std::log2(x); }
 inline Dual Log2(Dual x) { return {std::log2(x.v), x.d / (x.v * std::log(2.0))}; }
+
+// Forward-mode dual number carrying kDirs directions at once: the value (and every
+// transcendental of it) is computed once, each direction's derivative by the chain rule.
+constexpr int kDirs = 16;
+struct DualN {
+  double v;
+  double d[kDirs];
+  DualN() : v(0) { for (int q = 0; q < kDirs; ++q) d[q] = 0; }
+  DualN(double x) : v(x) { for (int q = 0; q < kDirs; ++q) d[q] = 0; }
+};
+inline DualN operator+(const DualN& a, const DualN& b) {
+  DualN r(a.v + b.v);
+  for (int q = 0; q < kDirs; ++q) r.d[q] = a.d[q] + b.d[q];
+  return r;
+}
+inline DualN operator-(const DualN& a, const DualN& b) {
+  DualN r(a.v - b.v);
+  for (int q = 0; q < kDirs; ++q) r.d[q] = a.d[q] - b.d[q];
+  return r;
+}
+inline DualN operator-(const DualN& a) {
+  DualN r(-a.v);
+  for (int q = 0; q < kDirs; ++q) r.d[q] = -a.d[q];
+  return r;
+}
+inline DualN operator*(const DualN& a, const DualN& b) {
+  DualN r(a.v * b.v);
+  for (int q = 0; q < kDirs; ++q) r.d[q] = a.d[q] * b.v + a.v * b.d[q];
+  return r;
+}
+inline DualN operator/(const DualN& a, const DualN& b) {
+  DualN r(a.v / b.v);
+  for (int q = 0; q < kDirs; ++q) r.d[q] = (a.d[q] * b.v - a.v * b.d[q]) / (b.v * b.v);
+  return r;
+}
+// products and sums with a constant (its derivative is zero)
+inline DualN operator*(const DualN& a, double b) {
+  DualN r(a.v * b);
+  for (int q = 0; q < kDirs; ++q) r.d[q] = a.d[q] * b;
+  return r;
+}
+inline DualN operator*(double a, const DualN& b) { return b * a; }
+inline DualN operator+(const DualN& a, double b) {
+  DualN r = a;
+  r.v += b;
+  return r;
+}
+inline DualN operator+(double a, const DualN& b) { return b + a; }
+inline DualN& operator+=(DualN& a, const DualN& b) { a = a + b; return a; }
+inline DualN& operator-=(DualN& a, const DualN& b) { a = a - b; return a; }
+inline DualN& operator*=(DualN& a, const DualN& b) { a = a * b; return a; }
+// f(a) with f'(a.v) = fp: the chain rule applied to every direction
+inline DualN Chain(const DualN& a, double f, double fp) {
+  DualN r(f);
+  for (int q = 0; q < kDirs; ++q) r.d[q] = fp * a.d[q];
+  return r;
+}
+inline double Val(const DualN& x) { return x.v; }
+inline DualN Exp(const DualN& x) { double e = std::exp(x.v); return Chain(x, e, e); }
+inline DualN Log(const DualN& x) { return Chain(x, std::log(x.v), 1.0 / x.v); }
+inline DualN Sinh(const DualN& x) { return Chain(x, std::sinh(x.v), std::cosh(x.v)); }
+inline DualN Log2(const DualN& x) { return Chain(x, std::log2(x.v), 1.0 / (x.v * std::log(2.0))); }
+
+// Derivative outputs: direction q of x goes to out[idx * stride + q].
+inline void PutDer(double, double* out, size_t idx) { out[idx] = 0.0; }
+inline void PutDer(const Dual& x, double* out, size_t idx) { out[idx] = x.d; }
+inline void PutDer(const DualN& x, double* out, size_t idx) {
+  for (int q = 0; q < kDirs; ++q) out[idx * kDirs + q] = x.d[q];
+}
 
 // sinh(x)/x with its limit 1 at x = 0.
 template <class T> T Sinhc(T x) {
@@ -520,6 +587,16 @@ std::vector<Dual> powers<Dual>(const orc_problem& pb) {
   for (int c = 0; c < pb.n_ch; ++c) P[c] = Dual(pb.p_w[c], pb.dp ? pb.dp[c] : 0.0);
   return P;
 }
+// pb.dp holds kDirs directions, row-major [q][c]
+template <>
+std::vector<DualN> powers<DualN>(const orc_problem& pb) {
+  std::vector<DualN> P(pb.n_ch);
+  for (int c = 0; c < pb.n_ch; ++c) {
+    P[c] = DualN(pb.p_w[c]);
+    for (int q = 0; q < kDirs; ++q) P[c].d[q] = pb.dp ? pb.dp[(size_t)q * pb.n_ch + c] : 0.0;
+  }
+  return P;
+}
 
 int n_workers(const orc_problem& pb) {
   int n = pb.n_threads > 0 ? pb.n_threads : (int)std::thread::hardware_concurrency();
@@ -580,7 +657,7 @@ int forward_impl(const orc_problem* pb, int n_coi, const int* coi, double* tiles
     for (int k = 0; k < N; ++k) {
       row += tl[(size_t)q * N + k];
       if (tiles) tiles[(size_t)q * N + k] = Val(tl[(size_t)q * N + k]);
-      if (dtiles) dtiles[(size_t)q * N + k] = Der(tl[(size_t)q * N + k]);
+      if (dtiles) PutDer(tl[(size_t)q * N + k], dtiles, (size_t)q * N + k);
     }
     const Channels& ch = md.ch;
     // eq. (gain_fin) times the COI bandwidth (locally white NLI)
@@ -597,14 +674,14 @@ int forward_impl(const orc_problem* pb, int n_coi, const int* coi, double* tiles
       tsum += Log2(T(1.0) + sn) * (2.0 * ch.R[i]);  // eq. (loss) and C = 2 B_ch (-L)
     }
     if (pnli) pnli[q] = Val(pn);
-    if (dpnli) dpnli[q] = Der(pn);
+    if (dpnli) PutDer(pn, dpnli, q);
     if (eta) eta[q] = Val(et);
-    if (deta) deta[q] = Der(et);
+    if (deta) PutDer(et, deta, q);
     if (snr) snr[q] = Val(sn);
-    if (dsnr) dsnr[q] = Der(sn);
+    if (dsnr) PutDer(sn, dsnr, q);
   }
   if (thr) *thr = Val(tsum);
-  if (dthr) *dthr = Der(tsum);
+  if (dthr) PutDer(tsum, dthr, 0);
   return 0;
 }
 
@@ -689,6 +766,22 @@ int orc_forward_dual(const orc_problem* pb, int n_coi, const int* coi, double* t
   return forward_impl<Dual>(pb, n_coi, coi, tiles, dtiles, pnli, dpnli, nullptr, nullptr, snr, dsnr,
                             thr, dthr, nullptr, nullptr);
 }
+
+// The same with up to kDirs directions in one pass: dirs is [n_dirs][n_ch] (the rest zero);
+// dtiles [n_coi * n_ch][kDirs], dpnli and dsnr [n_coi][kDirs], dthr [kDirs].
+int orc_forward_dualn(const orc_problem* pb, int n_dirs, const double* dirs, int n_coi, const int* coi,
+                      double* tiles, double* dtiles, double* pnli, double* dpnli, double* snr, double* dsnr,
+                      double* thr, double* dthr) {
+  if (!pb || !dirs || n_dirs < 1 || n_dirs > kDirs) return -1;
+  std::vector<double> d((size_t)kDirs * pb->n_ch, 0.0);
+  std::copy(dirs, dirs + (size_t)n_dirs * pb->n_ch, d.begin());
+  orc_problem local = *pb;
+  local.dp = d.data();
+  return forward_impl<DualN>(&local, n_coi, coi, tiles, dtiles, pnli, dpnli, nullptr, nullptr, snr, dsnr,
+                             thr, dthr, nullptr, nullptr);
+}
+
+int orc_max_dirs(void) { return kDirs; }
 
 // Integrand Psi(x, y) for COI i (G products included), for symmetry checks.
 int orc_psi(const orc_problem* pb, int i, int n, const double* x, const double* y, double* out) {

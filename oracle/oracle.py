@@ -62,6 +62,8 @@ def lib():
         L.orc_lnrho.argtypes = [P, C.c_int, _ip, _dp, _dp]
         L.orc_forward.argtypes = [P, C.c_int, _ip, _dp, _dp, _dp, _dp, _dp]
         L.orc_forward_dual.argtypes = [P, C.c_int, _ip] + [_dp] * 8
+        L.orc_forward_dualn.argtypes = [P, C.c_int, _dp, C.c_int, _ip] + [_dp] * 8
+        L.orc_max_dirs.restype = C.c_int
         L.orc_tiles.argtypes = [P, C.c_int, _ip, _ip, _dp]
         L.orc_psi.argtypes = [P, C.c_int, C.c_int, _dp, _dp, _dp]
         L.orc_paper_quadrants.argtypes = [P, C.c_int, _dp]
@@ -169,6 +171,25 @@ class Oracle:
         assert rc == 0
         return dict(coi=coi, tiles=tiles, dtiles=dtiles, pnli=pnli, dpnli=dpnli, snr=snr, dsnr=dsnr,
                     thr=thr.value, dthr=dthr.value)
+
+    def forward_dualn(self, directions: np.ndarray, coi: Optional[Sequence[int]] = None) -> dict:
+        """forward_dual along several directions (rows of `directions`, at most 16) in one pass:
+        dtiles [q, n, dir], dpnli and dsnr [q, dir], dthr [dir]."""
+        d = _arr(np.atleast_2d(directions))
+        nd = d.shape[0]
+        assert d.shape[1] == self.n and 1 <= nd <= lib().orc_max_dirs()
+        K = lib().orc_max_dirs()
+        coi = np.arange(self.n, dtype=np.int32) if coi is None else np.ascontiguousarray(np.asarray(coi, dtype=np.int32))
+        q = len(coi)
+        tiles, dtiles = np.zeros((q, self.n)), np.zeros((q, self.n, K))
+        pnli, dpnli, snr, dsnr = np.zeros(q), np.zeros((q, K)), np.zeros(q), np.zeros((q, K))
+        thr, dthr = C.c_double(), np.zeros(K)
+        rc = lib().orc_forward_dualn(C.byref(self.pb), nd, _ptr(d), q, coi.ctypes.data_as(_ip), _ptr(tiles),
+                                     _ptr(dtiles), _ptr(pnli), _ptr(dpnli), _ptr(snr), _ptr(dsnr), C.byref(thr),
+                                     _ptr(dthr))
+        assert rc == 0
+        return dict(coi=coi, tiles=tiles, dtiles=dtiles[:, :, :nd], pnli=pnli, dpnli=dpnli[:, :nd], snr=snr,
+                    dsnr=dsnr[:, :nd], thr=thr.value, dthr=dthr[:nd])
 
     def tiles(self, coi: Sequence[int], intf: Sequence[int]) -> np.ndarray:
         """tile(coi[q], intf[q]) for a list of pairs (the rows of forward() restricted to those pairs)."""

@@ -48,15 +48,19 @@ class Throughput(torch.nn.Module):
 def optimise_launch_power(engine: B.Engine, plan: W.Plan, p_dbm0, steps: int = 50, lr_db: float = 0.05,
                           lo_dbm: float = -5.0, hi_dbm: float = 5.0, snr_trx_lin: float = 0.0, progress=None):
     """Projected gradient ascent (Adam) of the total throughput over per-channel launch powers in
-    dBm, bounded to [lo_dbm, hi_dbm] as in Sec. IV.  Returns (p_dbm, history of throughput).
+    dBm, bounded to [lo_dbm, hi_dbm] as in Sec. IV.  Channels starting at -inf dBm (P = 0) are
+    empty (guard) channels and stay empty.  Returns (p_dbm, history of throughput).
     progress(step, throughput) is called after each step when given."""
     model = Throughput(engine, plan, snr_trx_lin)
-    x = torch.tensor(np.asarray(p_dbm0, dtype=np.float64), device="cuda", requires_grad=True)
+    p0 = np.asarray(p_dbm0, dtype=np.float64)
+    occupied = np.isfinite(p0)
+    occ = torch.tensor(occupied, device="cuda")
+    x = torch.tensor(np.where(occupied, p0, lo_dbm), device="cuda", requires_grad=True)
     opt = torch.optim.Adam([x], lr=lr_db)
     hist = []
     for _ in range(steps):
         opt.zero_grad()
-        P = 1e-3 * torch.pow(10.0, x / 10.0)
+        P = torch.where(occ, 1e-3 * torch.pow(10.0, x / 10.0), torch.zeros_like(x))
         thr, _ = model(P)
         total = thr.sum()
         (-total).backward()
@@ -66,4 +70,4 @@ def optimise_launch_power(engine: B.Engine, plan: W.Plan, p_dbm0, steps: int = 5
         hist.append(total.item())
         if progress:
             progress(len(hist), hist[-1])
-    return x.detach().cpu().numpy(), hist
+    return np.where(occupied, x.detach().cpu().numpy(), -np.inf), hist

@@ -8,7 +8,10 @@
   edges, L-BFGS-B with bounds +-5 dBm and stop at max|grad L| <= 0.01 -- but with the
   exact adjoint gradient instead of finite differences.
 
-    python -m paper_2401_18022_amd.optimise [--grid 64] [--steps 50] [--lbfgsb | --two-stage]
+    python -m paper_2401_18022_amd.optimise [--grid 64] [--steps 50] [--lbfgsb | --two-stage] [--guards]
+
+--guards runs the O-to-U plan with the paper's 32 empty guard channels (Table I), whose occupied
+channels per band give Table II's 23/10/6/3/4/3 segments.
 """
 from __future__ import annotations
 
@@ -42,15 +45,17 @@ def segment_counts(channels_per_band, spacing_hz: float = 100e9):
     return out
 
 
-def segment_matrix(f_hz: np.ndarray, spacing_hz: float = 100e9):
+def segment_matrix(f_hz: np.ndarray, spacing_hz: float = 100e9, occupied=None):
     """Interpolation matrix A (n_ch x n_edges): channel dBm = A @ edge dBm (linear in frequency
-    between equally spaced edges of each band)."""
+    between equally spaced edges of each band).  Only occupied channels (default: all) count
+    towards a band's width and get a row; the rows of empty (guard) channels are zero."""
     bands = band_of(f_hz)
-    counts = segment_counts([int(np.sum(bands == b)) for b in range(len(W.BAND_EDGES_NM))], spacing_hz)
+    occ = np.ones(len(f_hz), dtype=bool) if occupied is None else np.asarray(occupied, dtype=bool)
+    counts = segment_counts([int(np.sum((bands == b) & occ)) for b in range(len(W.BAND_EDGES_NM))], spacing_hz)
     cols, col0 = [], 0
     A = np.zeros((len(f_hz), sum(counts)))
     for b, ne in enumerate(counts):
-        idx = np.nonzero(bands == b)[0]
+        idx = np.nonzero((bands == b) & occ)[0]
         if len(idx) == 0:
             continue
         fe = np.linspace(f_hz[idx[0]], f_hz[idx[-1]], ne)
@@ -95,20 +100,24 @@ def fd_check(plan, fibre, channels, rel_step=10 ** 1e-4 - 1):
     return rows
 
 
-def segment_lbfgsb(engine, plan, x0_dbm=None, lo=-5.0, hi=5.0, pgtol=0.01, maxiter=200, progress=None):
-    """Minimise L = -sum log2(1 + SNR_i) (eq. loss) over segment edges in dBm."""
+def segment_powers(A, occupied, x):
+    """Channel powers (W) from segment edges x (dBm): interpolated in dBm, 0 W on empty channels."""
+    return np.where(occupied, 1e-3 * np.power(10.0, (A @ x) / 10.0), 0.0)
+
+
+def segment_objective(engine, plan, A, occupied, hist=None, progress=None):
+    """fg(x) -> (L, dL/dx): the cost of eq. (loss), L = -sum over occupied channels of
+    log2(1 + SNR_i), and its gradient with respect to the segment edges in dBm, through the
+    adjoint: dL/dx = A^T (dL/dP_k P_k ln10/10)."""
     import torch
-    from scipy.optimize import minimize
-    A, counts = segment_matrix(plan.f_hz)
     nf = torch.tensor(plan.nf_lin, dtype=torch.float64, device="cuda")
     bch = float(plan.rs_hz[0])
-    hist = []
+    hist = [] if hist is None else hist
 
     def fg(x):
         if progress:
             progress(len(hist), hist[-1] if hist else float("nan"))
-        p_dbm = A @ x
-        P = 1e-3 * np.power(10.0, p_dbm / 10.0)
+        P = segment_powers(A, occupied, np.asarray(x, dtype=np.float64))
         snr, thr, g = engine.snr_grad(plan, torch.tensor(P, dtype=torch.float64, device="cuda"), nf)
         T = float(thr.sum().item())
         gP = g.cpu().numpy()
@@ -117,10 +126,22 @@ def segment_lbfgsb(engine, plan, x0_dbm=None, lo=-5.0, hi=5.0, pgtol=0.01, maxit
         hist.append(T)
         return loss, A.T @ dloss_dp
 
+    return fg
+
+
+def segment_lbfgsb(engine, plan, x0_dbm=None, lo=-5.0, hi=5.0, pgtol=0.01, maxiter=200, progress=None):
+    """Minimise L = -sum log2(1 + SNR_i) (eq. loss) over segment edges in dBm.  Channels launched
+    at P = 0 are empty (guard) channels: they stay empty and do not count towards the segments."""
+    from scipy.optimize import minimize
+    occupied = np.asarray(plan.p_w) > 0
+    A, counts = segment_matrix(plan.f_hz, occupied=occupied)
+    hist = []
+    fg = segment_objective(engine, plan, A, occupied, hist, progress)
     x0 = np.zeros(A.shape[1]) if x0_dbm is None else np.asarray(x0_dbm, dtype=np.float64)
     res = minimize(fg, x0, jac=True, method="L-BFGS-B", bounds=[(lo, hi)] * A.shape[1],
                    options=dict(gtol=pgtol, maxiter=maxiter))
-    return res.x, A @ res.x, hist, res, counts
+    p_dbm = np.where(occupied, A @ res.x, -np.inf)
+    return res.x, p_dbm, hist, res, counts
 
 
 def two_stage(fibre, plan, coarse: dict, fine: dict, progress=None, maxiter=200):
@@ -154,9 +175,12 @@ def main(argv=None):
     ap.add_argument("--no-fp64-check", action="store_true", help="skip the FP64-form re-check")
     ap.add_argument("--fd-check", type=int, default=0, metavar="N",
                     help="only compare the adjoints with FP64 central differences on N seeded channels")
+    ap.add_argument("--guards", action="store_true", help="the O-to-U plan with 32 empty guard channels")
     args = ap.parse_args(argv)
-    wl = W.config_ou(grid_s=args.grid, grid_v=args.grid, n_steps=args.n_steps)
-    out = {"workload": f"O-to-U 589 ch, G={args.grid}, N_M={args.n_steps}, FP32 form"}
+    make = W.config_ou_guarded if args.guards else W.config_ou
+    wl = make(grid_s=args.grid, grid_v=args.grid, n_steps=args.n_steps)
+    out = {"workload": f"O-to-U 589 ch{' (32 guard)' if args.guards else ''}, G={args.grid}, N_M={args.n_steps}, "
+                       "FP32 form"}
 
     def note(k, thr):
         print(f"[optimise] evaluation {k}: throughput {thr / 1e12:.4f} Tb/s", file=sys.stderr, flush=True)
@@ -184,7 +208,7 @@ def main(argv=None):
         print(json.dumps(out), flush=True)
         return
     eng = B.Engine(wl.fibre, W.FP32)
-    p0 = 10 * np.log10(wl.plan.p_w / 1e-3)
+    p0 = np.where(wl.plan.p_w > 0, 10 * np.log10(np.maximum(wl.plan.p_w, 1e-300) / 1e-3), -np.inf)
     t0 = time.perf_counter()
     if args.lbfgsb:
         x, p_dbm, hist, res, counts = segment_lbfgsb(eng, wl.plan, progress=note)
@@ -203,7 +227,8 @@ def main(argv=None):
     if not args.no_fp64_check:  # the optimised powers re-evaluated with the FP64 form
         e64 = B.Engine(wl.fibre, W.FP64)
         snr64, thr64 = e64.snr(plan, P, nf)
-        d = 10 * np.log10(snr32.cpu().numpy() / snr64.cpu().numpy())
+        occ = plan.p_w > 0
+        d = 10 * np.log10(snr32.cpu().numpy()[occ] / snr64.cpu().numpy()[occ])
         out["fp64_recheck"] = {"throughput_tbps": thr64.item() / 1e12, "max_abs_dsnr_db": float(np.abs(d).max())}
     print(json.dumps(out), flush=True)
 

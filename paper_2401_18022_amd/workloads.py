@@ -247,6 +247,32 @@ def config_ou(seed: int = 3, **fib) -> Workload:
     return Workload("ou-589ch", ou_fibre(**fib), plan, "589 ch O-to-U, ODE profile, G=128, N_M=112")
 
 
+# Table I: 32 guard channels, 5 nm guard-band gaps.  The paper gives the gap width and, in Table II,
+# the occupied channels per band (171/143/88/38/65/52), not where the gaps sit: on this grid the
+# gaps [e - 2, e + 3) nm at the interior ITU band edges e (and [1457.5, 1462.5) at 1460 nm) leave
+# exactly those counts.
+GUARD_GAPS_NM = [(1358.0, 1363.0), (1457.5, 1462.5), (1528.0, 1533.0), (1563.0, 1568.0), (1623.0, 1628.0)]
+
+
+def guard_mask(f_hz: np.ndarray) -> np.ndarray:
+    """True for the channels whose centre lies in one of the guard-band gaps."""
+    lam_nm = C_LIGHT / np.asarray(f_hz) * 1e9
+    m = np.zeros(len(lam_nm), dtype=bool)
+    for lo, hi in GUARD_GAPS_NM:
+        m |= (lam_nm >= lo) & (lam_nm < hi)
+    return m
+
+
+def config_ou_guarded(seed: int = 3, **fib) -> Workload:
+    """The O-to-U system with the paper's 32 empty guard channels (P = 0, the set A of eq. loss) at the
+    band edges; the 557 occupied channels launch i.i.d. U(-2,+2) dBm."""
+    rng = np.random.default_rng(seed)
+    f = ou_grid()
+    p = np.where(guard_mask(f), 0.0, dbm_to_w(rng.uniform(-2.0, 2.0, size=589)))
+    plan = single_plan(f, 96e9, p, nf_by_band(f))
+    return Workload("ou-589ch-guarded", ou_fibre(**fib), plan, "589 ch O-to-U, 32 guard channels, G=128, N_M=112")
+
+
 def fd_channels(seed: int = 4, n_ch: int = 589, count: int = 16) -> np.ndarray:
     """The seeded channels on which finite differences check the adjoint gradient."""
     return np.sort(np.random.default_rng(seed).choice(n_ch, count, replace=False))

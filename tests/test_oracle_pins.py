@@ -454,6 +454,28 @@ def test_dual_gradient_matches_central_differences(profile):
     np.testing.assert_allclose(r["dtiles"], (tp["tiles"] - tm["tiles"]) / (2 * h), rtol=1e-5, atol=1e-9 * np.abs(r["dtiles"]).max())
 
 
+@pytest.mark.parametrize("profile", [W.PROFILE_CLOSED_FORM, W.PROFILE_ODE])
+def test_multi_direction_duals_match_central_differences(profile):
+    """The 16-wide dual type: every direction's derivative equals central differences (as the
+    scalar dual's does above), directions left zero give zero, and the scalar dual agrees."""
+    wl = W.random_small(6, seed=23, profile=profile, grid_s=10, grid_v=10, n_steps=10)
+    plan = wl.plan.with_power(wl.plan.p_w * 30)
+    o = O.Oracle(wl.fibre, plan)
+    rng = np.random.default_rng(5)
+    dirs = rng.normal(size=(3, 6)) * plan.p_w
+    r = o.forward_dualn(dirs)
+    assert r["dthr"].shape == (3,) and r["dsnr"].shape == (6, 3)
+    h = 1e-5
+    for q in range(3):
+        tp = O.Oracle(wl.fibre, plan.with_power(plan.p_w + h * dirs[q])).forward()
+        tm = O.Oracle(wl.fibre, plan.with_power(plan.p_w - h * dirs[q])).forward()
+        assert r["dthr"][q] == pytest.approx((tp["thr"] - tm["thr"]) / (2 * h), rel=1e-6)
+        np.testing.assert_allclose(r["dsnr"][:, q], (tp["snr"] - tm["snr"]) / (2 * h), rtol=1e-6)
+        assert r["dthr"][q] == pytest.approx(o.forward_dual(dirs[q])["dthr"], rel=1e-13)
+    z = o.forward_dualn(np.vstack([dirs[:1], np.zeros((1, 6))]))
+    assert z["dthr"][1] == 0.0 and np.all(z["dtiles"][:, :, 1] == 0.0)
+
+
 # ----------------------------------------------------------------------------- several spans
 def test_spans_sum_to_the_phased_array_factor():
     """n identical spans (App. A, eq. gain summed over spans with offsets (k-1) L): the oracle
