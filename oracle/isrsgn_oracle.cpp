@@ -30,7 +30,12 @@
 //     P2 profile = RK4 on the Raman ODEs (triangular gain with cut-off,
 //     photon-number ratio, A_eff scaling), ln rho interpolated linearly in f
 //     between channel centres;
-//   * NLI power = R_i G(f_i); ASE = NF h f G_amp R with G_amp = 1/rho(L, f);
+//   * transmit spectra: unit-area raised-cosine shape of roll-off beta (the PSD of an RRC-filtered
+//     signal; beta = 0 is the paper's rectangle), G_Tx = P_c g_c(f - f_c) on |f - f_c| < (1+beta) R_c/2;
+//   * noise powers are PSDs integrated against the receiver's power response R_i g_i(f - f_i)
+//     (unit passband, noise bandwidth R_i): ASE = NF h f G_amp R with G_amp = 1/rho(L, f); NLI by a
+//     normalised midpoint rule over nli_points points across the COI's support, whose one-point
+//     form is the locally-white R_i G(f_i);
 //   * n identical spans: each amplifier restores the launch power, so every span has the same
 //     power profile and adds the same ASE; span k's field carries the phase phi (k-1) L.
 #include <algorithm>
@@ -74,6 +79,8 @@ inline double Log(double x) { return std::log(x); }
 inline Dual Log(Dual x) { return {std::log(x.v), x.d / x.v}; }
 inline double Sinh(double x) { return std::sinh(x); }
 inline Dual Sinh(Dual x) { return {std::sinh(x.v), std::cosh(x.v) * x.d}; }
+inline double Cosh(double x) { return std::cosh(x); }
+inline Dual Cosh(Dual x) { return {std::cosh(x.v), std::sinh(x.v) * x.d}; }
 inline double Log2(double x) { return std::log2(x); }
 inline Dual Log2(Dual x) { return {std::log2(x.v), x.d / (x.v * std::log(2.0))}; }
 
@@ -137,6 +144,7 @@ inline double Val(const DualN& x) { return x.v; }
 inline DualN Exp(const DualN& x) { double e = std::exp(x.v); return Chain(x, e, e); }
 inline DualN Log(const DualN& x) { return Chain(x, std::log(x.v), 1.0 / x.v); }
 inline DualN Sinh(const DualN& x) { return Chain(x, std::sinh(x.v), std::cosh(x.v)); }
+inline DualN Cosh(const DualN& x) { return Chain(x, std::cosh(x.v), std::sinh(x.v)); }
 inline DualN Log2(const DualN& x) { return Chain(x, std::log2(x.v), 1.0 / (x.v * std::log(2.0))); }
 
 // Derivative outputs: direction q of x goes to out[idx * stride + q].
@@ -153,6 +161,20 @@ template <class T> T Sinhc(T x) {
     return T(1.0) + x2 * (1.0 / 6.0) + x2 * x2 * (1.0 / 120.0);
   }
   return Sinh(x) / x;
+}
+
+// Two-sided Laplace transform M(a) = int g(u) exp(-a u) du of the unit-area raised-cosine
+// spectrum g of symbol rate R and roll-off beta.  g is the rectangle of width R (transform
+// sinhc(a R/2)) convolved with the unit half-cosine lobe (pi / (2 beta R)) cos(pi v / (beta R)) on
+// |v| <= beta R/2 (transform cosh(a beta R/2) / (1 + (a beta R/pi)^2)); beta = 0 leaves sinhc.
+template <class T> T Spectrum(T a, double R, double beta) {
+  T m = Sinhc(a * (0.5 * R));
+  if (beta > 0) {
+    const double h = 0.5 * beta * R, c = beta * R / 3.14159265358979323846;
+    T ac = a * c;
+    m = m * Cosh(a * h) / (T(1.0) + ac * ac);
+  }
+  return m;
 }
 
 }  // namespace
@@ -177,6 +199,8 @@ typedef struct {
   int unfold;  // 1: evaluate both sides of each fold explicitly (symmetry check)
   int mode;    // 0: model integrand; 1: unit integrand; 2: unit integrand on the channel support
   int n_spans;  // identical spans (App. A, eq. gain: sum over spans k with offsets (k-1) L)
+  double rolloff;   // raised-cosine roll-off of every transmit spectrum (0: rectangular)
+  int nli_points;   // points of the within-channel NLI rule (1: locally white at the centre)
 } orc_problem;
 
 }  // extern "C"
@@ -201,12 +225,26 @@ double table_at(int n, const double* xs, const double* ys, double x) {
 
 struct Channels {
   int n;
+  double beta;  // roll-off of the transmit spectra
   std::vector<double> f, R, alpha, aeff, gamma, cr, nf;
+  // half-width of channel c's support
+  double half(int c) const { return 0.5 * (1.0 + beta) * R[c]; }
+  // unit-area spectral shape of channel c at absolute frequency F: the raised cosine
+  // (1/R) on |u| <= (1-beta) R/2, (1/R) (1 + cos(pi (|u| - (1-beta) R/2) / (beta R))) / 2 up to
+  // (1+beta) R/2, zero beyond (u = F - f_c); beta = 0 is the rectangle of width R
+  double shape(int c, double F) const {
+    const double u = std::fabs(F - f[c]), r = R[c];
+    if (u >= half(c)) return 0.0;
+    const double flat = 0.5 * (1.0 - beta) * r;
+    if (u <= flat) return 1.0 / r;
+    return 0.5 * (1.0 + std::cos(kPi * (u - flat) / (beta * r))) / r;
+  }
 };
 
 Channels make_channels(const orc_problem& pb) {
   Channels ch;
   ch.n = pb.n_ch;
+  ch.beta = pb.rolloff;
   for (int c = 0; c < pb.n_ch; ++c) {
     double f = pb.f_hz[c];
     ch.f.push_back(f);
@@ -292,9 +330,10 @@ struct Profile {
   }
 };
 
-// P1: closed-form ISRS solution for a linear Raman gain slope over a rectangular
-// spectrum (the draft-comment expression of App. A, Zirngibl 1998):
+// P1: closed-form ISRS solution for a linear Raman gain slope (the draft-comment expression of
+// App. A, Zirngibl 1998), for rectangular spectra:
 //   rho(z,F) = exp(-alpha z) exp(-a (F - f_ref)) / sum_j (P_j/P_tot) exp(-a (f_j - f_ref)) sinhc(a R_j / 2)
+// and for raised-cosine spectra with sinhc(a R_j/2) replaced by the spectrum's transform M_j(a)
 //   a(z) = P_tot C_r L_eff(z),  L_eff(z) = (1 - exp(-alpha z)) / alpha
 template <class T>
 void closed_form_at(const Channels& ch, const std::vector<T>& P, double alpha, double cr, double f_ref,
@@ -306,7 +345,7 @@ void closed_form_at(const Channels& ch, const std::vector<T>& P, double alpha, d
   T a = ptot * (cr * leff);
   T norm(0.0);
   for (int j = 0; j < ch.n; ++j)
-    norm += P[j] / ptot * Exp(-a * (ch.f[j] - f_ref)) * Sinhc(a * (0.5 * ch.R[j]));
+    norm += P[j] / ptot * Exp(-a * (ch.f[j] - f_ref)) * Spectrum(a, ch.R[j], ch.beta);
   *a_out = a;
   *lnnorm_out = Log(norm);
 }
@@ -396,15 +435,45 @@ double phase_mismatch(double x, double y, double w, double b2, double b3, double
   return -4.0 * kPi * kPi * x * y * (b2 + kPi * b3 * (x + y + 2.0 * w) + (2.0 * kPi * kPi / 3.0) * b4 * poly4);
 }
 
-// Channel whose rectangular PSD [f_c - R_c/2, f_c + R_c/2) holds F, or -1 (gap / outside).
+// Channel whose spectrum's support [f_c - (1+beta) R_c/2, f_c + (1+beta) R_c/2) holds F, or -1.
 int channel_of(const Channels& ch, double F) {
   int lo = 0, hi = ch.n;  // find the last channel whose lower edge <= F
-  if (F < ch.f[0] - 0.5 * ch.R[0]) return -1;
+  if (F < ch.f[0] - ch.half(0)) return -1;
   while (hi - lo > 1) {
     int mid = (lo + hi) / 2;
-    if (ch.f[mid] - 0.5 * ch.R[mid] <= F) lo = mid; else hi = mid;
+    if (ch.f[mid] - ch.half(mid) <= F) lo = mid; else hi = mid;
   }
-  return F < ch.f[lo] + 0.5 * ch.R[lo] ? lo : -1;
+  return F < ch.f[lo] + ch.half(lo) ? lo : -1;
+}
+
+// Points and weights of the within-channel NLI rule of COI i: n midpoints across the support
+// [f_i - (1+beta) R_i/2, f_i + (1+beta) R_i/2], weights proportional to the receiver's power
+// response R_i g_i(f - f_i) and normalised to its noise bandwidth R_i (so a flat NLI PSD is
+// integrated exactly, and one point is the locally-white R_i G(f_i)).
+void nli_points(const Channels& ch, int i, int n, std::vector<double>* f, std::vector<double>* q) {
+  f->assign(n, 0.0);
+  q->assign(n, 0.0);
+  const double d = 2.0 * ch.half(i) / n;
+  double sum = 0.0;
+  for (int j = 0; j < n; ++j) {
+    (*f)[j] = ch.f[i] - ch.half(i) + (j + 0.5) * d;
+    (*q)[j] = ch.R[i] * ch.shape(i, (*f)[j]);
+    sum += (*q)[j];
+  }
+  for (int j = 0; j < n; ++j) (*q)[j] *= ch.R[i] / sum;
+}
+
+// Transmit PSD of channel c at F: P_c / R_c for the rectangle, P_c g_c(F - f_c) in general.
+template <class T>
+T density(const Channels& ch, const std::vector<T>& P, int c, double F) {
+  if (ch.beta == 0.0) return P[c] / ch.R[c];
+  return P[c] * ch.shape(c, F);
+}
+
+// gamma at an arbitrary frequency: eq. (gamma) with A_eff interpolated from the table, or the constant.
+double gamma_at(const orc_problem& pb, double f) {
+  double ae = table_at(pb.n_tab, pb.tab_f_hz, pb.tab_aeff_m2, f);
+  return pb.gamma_const > 0 ? pb.gamma_const : 2.0 * kPi * pb.n2 * f / (kC * ae);
 }
 
 // ---------------------------------------------------------------------------
@@ -475,17 +544,17 @@ struct Model {
   Steps st;
 };
 
-// Psi of eq. (psi_fin) without the COI PSD factor: G(f1) G(f2) G(f3) |S|^2 for COI i.
+// Psi of eq. (psi_fin) at NLI frequency fi: G_Tx(f1) G_Tx(f2) G_Tx(f1+f2-fi) |S|^2, offsets x, y
+// from fi.  P: channel powers (G_Tx = P_c times the channel's unit shape).
 template <class T>
-T psi(const Model& md, const Profile<T>& pr, const std::vector<T>& G, int i, double x, double y) {
+T psi(const Model& md, const Profile<T>& pr, const std::vector<T>& P, double fi, double x, double y) {
   const Channels& ch = md.ch;
   const orc_problem& pb = *md.pb;
-  double fi = ch.f[i];
   int c1 = channel_of(ch, fi + x), c2 = channel_of(ch, fi + y), c3 = channel_of(ch, fi + x + y);
   if (pb.mode == 1) return T(1.0);
   if (c1 < 0 || c2 < 0 || c3 < 0) return T(0.0);
   if (pb.mode == 2) return T(1.0);
-  T gprod = G[c1] * G[c2] * G[c3];
+  T gprod = density(ch, P, c1, fi + x) * density(ch, P, c2, fi + y) * density(ch, P, c3, fi + x + y);
   double phi = phase_mismatch(x, y, fi - pb.f_ref_hz, pb.beta2, pb.beta3, pb.beta4);
   T sre(0.0), sim(0.0);
   // eq. (psi_fin): sum over the n identical spans (offset (k-1) L, the same power profile in
@@ -507,16 +576,17 @@ T psi(const Model& md, const Profile<T>& pr, const std::vector<T>& G, int i, dou
   return gprod * (sre * sre + sim * sim);
 }
 
-// tile(i,k): Riemann sum of Psi over the tile's parts (without the 16/27 gamma^2 R_i factor).
+// tile(fi, k): Riemann sum of Psi at NLI frequency fi over the part of the band square where
+// f1 + f2 - fi lies in channel k (without the 16/27 gamma^2 factor).
 template <class T>
-T tile_integral(const Model& md, const Profile<T>& pr, const std::vector<T>& G, int i, int k) {
+T tile_integral(const Model& md, const Profile<T>& pr, const std::vector<T>& P, double fi, int k) {
   const Channels& ch = md.ch;
   const orc_problem& pb = *md.pb;
   const int n = ch.n;
-  double xp = (ch.f[n - 1] + 0.5 * ch.R[n - 1]) - ch.f[i];
-  double xn = ch.f[i] - (ch.f[0] - 0.5 * ch.R[0]);
-  double delta = ch.f[k] - ch.f[i];
-  double slo = delta - 0.5 * ch.R[k], shi = delta + 0.5 * ch.R[k];
+  double xp = (ch.f[n - 1] + ch.half(n - 1)) - fi;
+  double xn = fi - (ch.f[0] - ch.half(0));
+  double delta = ch.f[k] - fi;
+  double slo = delta - ch.half(k), shi = delta + ch.half(k);
   T total(0.0);
   for (int part = kQ1; part <= kQ4; ++part) {
     double umax;
@@ -534,9 +604,9 @@ T tile_integral(const Model& md, const Profile<T>& pr, const std::vector<T>& G, 
         part_map(part, r, v, &x, &y);
         double w = std::exp(s) * ds * dv;
         if (pb.unfold) {  // the fold partner (y, x) evaluated explicitly
-          total += (psi(md, pr, G, i, x, y) + psi(md, pr, G, i, y, x)) * w;
+          total += (psi(md, pr, P, fi, x, y) + psi(md, pr, P, fi, y, x)) * w;
         } else {
-          total += psi(md, pr, G, i, x, y) * (2.0 * w);
+          total += psi(md, pr, P, fi, x, y) * (2.0 * w);
         }
       }
     }
@@ -544,14 +614,14 @@ T tile_integral(const Model& md, const Profile<T>& pr, const std::vector<T>& G, 
   return total;
 }
 
-// Paper-literal quadrants of eqs. (q1)-(q4) for COI i over the whole band square,
+// Paper-literal quadrants of eqs. (q1)-(q4) at NLI frequency fi over the whole band square,
 // same node rule (D decades below the quadrant's sup|x y|, uniform in upsilon2).
-double paper_quadrant(const Model& md, const Profile<double>& pr, const std::vector<double>& G, int i, int q) {
+double paper_quadrant(const Model& md, const Profile<double>& pr, const std::vector<double>& P, double fi, int q) {
   const Channels& ch = md.ch;
   const orc_problem& pb = *md.pb;
   const int n = ch.n;
-  double bp = (ch.f[n - 1] + 0.5 * ch.R[n - 1]) - ch.f[i];  // the paper's B - f
-  double bm = ch.f[i] - (ch.f[0] - 0.5 * ch.R[0]);          // the paper's B + f
+  double bp = (ch.f[n - 1] + ch.half(n - 1)) - fi;  // the paper's B - f
+  double bm = fi - (ch.f[0] - ch.half(0));          // the paper's B + f
   // (f1 limit, f2 limit, sign of f1, sign of f2) per quadrant
   double l1[4] = {bp, bm, bm, bp}, l2[4] = {bp, bp, bm, bm};
   double s1[4] = {+1, -1, -1, +1}, s2[4] = {+1, +1, -1, -1};
@@ -568,7 +638,7 @@ double paper_quadrant(const Model& md, const Profile<double>& pr, const std::vec
     for (int b = 0; b < pb.grid_v; ++b) {
       double v = vlo + (b + 0.5) * dv;
       double g1 = r * std::exp(v), g2 = r * std::exp(-v);
-      total += psi(md, pr, G, i, s1[q] * g1, s2[q] * g2) * (std::exp(s) * ds * dv);
+      total += psi(md, pr, P, fi, s1[q] * g1, s2[q] * g2) * (std::exp(s) * ds * dv);
     }
   }
   return total;
@@ -619,8 +689,9 @@ void parallel_for(int count, int workers, F&& fn) {
 bool valid(const orc_problem* pb) {
   if (!pb || pb->n_ch < 1 || pb->n_steps < 1 || pb->grid_s < 1 || pb->grid_v < 1 || pb->ode_sub < 1) return false;
   if (pb->profile == 0 && pb->n_tab != 1) return false;  // the closed form needs uniform loss
-  for (int c = 0; c + 1 < pb->n_ch; ++c)
-    if (pb->f_hz[c + 1] - pb->f_hz[c] < 0.5 * (pb->rs_hz[c] + pb->rs_hz[c + 1])) return false;
+  if (!(pb->rolloff >= 0.0 && pb->rolloff <= 1.0) || pb->nli_points < 1) return false;
+  for (int c = 0; c + 1 < pb->n_ch; ++c)  // spectra may touch but not overlap
+    if (pb->f_hz[c + 1] - pb->f_hz[c] < 0.5 * (1.0 + pb->rolloff) * (pb->rs_hz[c] + pb->rs_hz[c + 1])) return false;
   return true;
 }
 
@@ -636,8 +707,6 @@ int forward_impl(const orc_problem* pb, int n_coi, const int* coi, double* tiles
   md.ch = make_channels(*pb);
   md.st = make_steps(mean_loss(md.ch, pb->p_w), pb->span_m, pb->n_steps);
   std::vector<T> P = powers<T>(*pb);
-  std::vector<T> G(pb->n_ch);
-  for (int c = 0; c < pb->n_ch; ++c) G[c] = P[c] / md.ch.R[c];  // rectangular PSD
   Profile<T> pr = make_profile(*pb, md.ch, P, md.st);
   const int N = pb->n_ch;
   if (ell_out)
@@ -646,10 +715,33 @@ int forward_impl(const orc_problem* pb, int n_coi, const int* coi, double* tiles
   if (ell_L_out)
     for (int c = 0; c < N; ++c) ell_L_out[c] = Val(pr.lnrho(-1, md.ch.f[c]));
   if (n_coi <= 0) return 0;
-  std::vector<T> tl((size_t)n_coi * N);
-  parallel_for(n_coi * N, n_workers(*pb), [&](int t) {
-    tl[t] = tile_integral(md, pr, G, coi[t / N], t % N);
+  // the within-channel rule: per COI q and point j the NLI frequency and the weight that turns
+  // tile(f_ij, k) into the COI's tile row: q_j gamma(f_ij)^2 / (gamma_i^2 R_i), so that
+  // P_NLI,i = 16/27 gamma_i^2 R_i sum_k row(k) (one point, rectangle: weight 1, f_i0 = f_i)
+  const int J = pb->nli_points;
+  std::vector<double> fpt((size_t)n_coi * J), wpt((size_t)n_coi * J);
+  for (int q = 0; q < n_coi; ++q) {
+    const int i = coi[q];
+    std::vector<double> fj, qj;
+    nli_points(md.ch, i, J, &fj, &qj);
+    for (int j = 0; j < J; ++j) {
+      const double gr = md.ch.gamma[i] > 0 ? gamma_at(*pb, fj[j]) / md.ch.gamma[i] : 1.0;
+      fpt[(size_t)q * J + j] = fj[j];
+      wpt[(size_t)q * J + j] = qj[j] * gr * gr / md.ch.R[i];
+    }
+  }
+  std::vector<T> tp((size_t)n_coi * J * N);
+  parallel_for(n_coi * J * N, n_workers(*pb), [&](int t) {
+    tp[t] = tile_integral(md, pr, P, fpt[t / N], t % N);
   });
+  std::vector<T> tl((size_t)n_coi * N);
+  for (int q = 0; q < n_coi; ++q)
+    for (int k = 0; k < N; ++k) {
+      T v(0.0);
+      for (int j = 0; j < J; ++j)
+        v += tp[((size_t)q * J + j) * N + k] * wpt[(size_t)q * J + j];
+      tl[(size_t)q * N + k] = v;
+    }
   T tsum(0.0);
   for (int q = 0; q < n_coi; ++q) {
     int i = coi[q];
@@ -660,7 +752,7 @@ int forward_impl(const orc_problem* pb, int n_coi, const int* coi, double* tiles
       if (dtiles) PutDer(tl[(size_t)q * N + k], dtiles, (size_t)q * N + k);
     }
     const Channels& ch = md.ch;
-    // eq. (gain_fin) times the COI bandwidth (locally white NLI)
+    // eq. (gain_fin) integrated over the COI's band by the within-channel rule
     T pn = row * ((16.0 / 27.0) * ch.gamma[i] * ch.gamma[i] * ch.R[i]);
     T pi = P[i];
     T et = Val(pi) > 0 ? pn / (pi * pi * pi) : T(std::numeric_limits<double>::quiet_NaN());
@@ -752,10 +844,23 @@ int orc_tiles(const orc_problem* pb, int n_pairs, const int* coi, const int* int
   md.ch = make_channels(*pb);
   md.st = make_steps(mean_loss(md.ch, pb->p_w), pb->span_m, pb->n_steps);
   std::vector<double> P = powers<double>(*pb);
-  std::vector<double> G(pb->n_ch);
-  for (int c = 0; c < pb->n_ch; ++c) G[c] = P[c] / md.ch.R[c];  // rectangular PSD
   Profile<double> pr = make_profile(*pb, md.ch, P, md.st);
-  parallel_for(n_pairs, n_workers(*pb), [&](int q) { out[q] = tile_integral(md, pr, G, coi[q], intf[q]); });
+  parallel_for(n_pairs, n_workers(*pb), [&](int q) { out[q] = tile_integral(md, pr, P, md.ch.f[coi[q]], intf[q]); });
+  return 0;
+}
+
+// tile(f[q], k[q]) at arbitrary NLI frequencies f inside the band (the within-channel rule's points).
+int orc_tiles_at(const orc_problem* pb, int n, const double* f, const int* k, double* out) {
+  if (!valid(pb)) return -1;
+  for (int q = 0; q < n; ++q)
+    if (k[q] < 0 || k[q] >= pb->n_ch) return -1;
+  Model md;
+  md.pb = pb;
+  md.ch = make_channels(*pb);
+  md.st = make_steps(mean_loss(md.ch, pb->p_w), pb->span_m, pb->n_steps);
+  std::vector<double> P = powers<double>(*pb);
+  Profile<double> pr = make_profile(*pb, md.ch, P, md.st);
+  parallel_for(n, n_workers(*pb), [&](int q) { out[q] = tile_integral(md, pr, P, f[q], k[q]); });
   return 0;
 }
 
@@ -791,10 +896,8 @@ int orc_psi(const orc_problem* pb, int i, int n, const double* x, const double* 
   md.ch = make_channels(*pb);
   md.st = make_steps(mean_loss(md.ch, pb->p_w), pb->span_m, pb->n_steps);
   std::vector<double> P = powers<double>(*pb);
-  std::vector<double> G(pb->n_ch);
-  for (int c = 0; c < pb->n_ch; ++c) G[c] = P[c] / md.ch.R[c];
   Profile<double> pr = make_profile(*pb, md.ch, P, md.st);
-  for (int q = 0; q < n; ++q) out[q] = psi(md, pr, G, i, x[q], y[q]);
+  for (int q = 0; q < n; ++q) out[q] = psi(md, pr, P, md.ch.f[i], x[q], y[q]);
   return 0;
 }
 
@@ -806,12 +909,49 @@ int orc_paper_quadrants(const orc_problem* pb, int i, double* q4) {
   md.ch = make_channels(*pb);
   md.st = make_steps(mean_loss(md.ch, pb->p_w), pb->span_m, pb->n_steps);
   std::vector<double> P = powers<double>(*pb);
-  std::vector<double> G(pb->n_ch);
-  for (int c = 0; c < pb->n_ch; ++c) G[c] = P[c] / md.ch.R[c];
   Profile<double> pr = make_profile(*pb, md.ch, P, md.st);
-  parallel_for(4, n_workers(*pb), [&](int q) { q4[q] = paper_quadrant(md, pr, G, i, q); });
+  parallel_for(4, n_workers(*pb), [&](int q) { q4[q] = paper_quadrant(md, pr, P, md.ch.f[i], q); });
   return 0;
 }
+
+// The same four quadrants at an arbitrary NLI frequency f inside the band (no tiles):
+// sum(q4) * 16/27 gamma(f)^2 is the NLI PSD G(f) of eq. (new_gn_model).
+int orc_paper_quadrants_at(const orc_problem* pb, double f, double* q4) {
+  if (!valid(pb)) return -1;
+  Model md;
+  md.pb = pb;
+  md.ch = make_channels(*pb);
+  md.st = make_steps(mean_loss(md.ch, pb->p_w), pb->span_m, pb->n_steps);
+  std::vector<double> P = powers<double>(*pb);
+  Profile<double> pr = make_profile(*pb, md.ch, P, md.st);
+  parallel_for(4, n_workers(*pb), [&](int q) { q4[q] = paper_quadrant(md, pr, P, f, q); });
+  return 0;
+}
+
+// The within-channel rule of channel c: points f_out[n] and weights q_out[n] (Hz).
+int orc_nli_points(const orc_problem* pb, int c, double* f_out, double* q_out) {
+  if (!valid(pb) || c < 0 || c >= pb->n_ch) return -1;
+  Channels ch = make_channels(*pb);
+  std::vector<double> f, q;
+  nli_points(ch, c, pb->nli_points, &f, &q);
+  for (int j = 0; j < pb->nli_points; ++j) { f_out[j] = f[j]; q_out[j] = q[j]; }
+  return 0;
+}
+
+// Transmit PSD of channel c at frequencies F[n] (W/Hz) and gamma at those frequencies.
+int orc_psd(const orc_problem* pb, int c, int n, const double* F, double* psd_out, double* gamma_out) {
+  if (!valid(pb) || c < 0 || c >= pb->n_ch) return -1;
+  Channels ch = make_channels(*pb);
+  std::vector<double> P = powers<double>(*pb);
+  for (int q = 0; q < n; ++q) {
+    if (psd_out) psd_out[q] = std::fabs(F[q] - ch.f[c]) < ch.half(c) ? density(ch, P, c, F[q]) : 0.0;
+    if (gamma_out) gamma_out[q] = gamma_at(*pb, F[q]);
+  }
+  return 0;
+}
+
+// The spectrum's Laplace transform M(a) of the closed-form profile (pins).
+double orc_spectrum_laplace(double a, double R, double beta) { return Spectrum(a, R, beta); }
 
 // gamma per channel (eq. gamma) for a problem.
 int orc_gamma(const orc_problem* pb, double* out) {

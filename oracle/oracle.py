@@ -32,7 +32,7 @@ class Problem(C.Structure):
         ("s_decades", C.c_double), ("ode_sub", C.c_int),
         ("n_ch", C.c_int), ("f_hz", _dp), ("rs_hz", _dp), ("p_w", _dp), ("nf_lin", _dp),
         ("snr_trx", C.c_double), ("dp", _dp), ("n_threads", C.c_int), ("unfold", C.c_int),
-        ("mode", C.c_int), ("n_spans", C.c_int),
+        ("mode", C.c_int), ("n_spans", C.c_int), ("rolloff", C.c_double), ("nli_points", C.c_int),
     ]
 
 
@@ -68,6 +68,12 @@ def lib():
         L.orc_psi.argtypes = [P, C.c_int, C.c_int, _dp, _dp, _dp]
         L.orc_paper_quadrants.argtypes = [P, C.c_int, _dp]
         L.orc_gamma.argtypes = [P, _dp]
+        L.orc_tiles_at.argtypes = [P, C.c_int, _dp, _ip, _dp]
+        L.orc_paper_quadrants_at.argtypes = [P, C.c_double, _dp]
+        L.orc_nli_points.argtypes = [P, C.c_int, _dp, _dp]
+        L.orc_psd.argtypes = [P, C.c_int, C.c_int, _dp, _dp, _dp]
+        L.orc_spectrum_laplace.argtypes = [C.c_double] * 3
+        L.orc_spectrum_laplace.restype = C.c_double
         _lib = L
     return _lib
 
@@ -120,6 +126,8 @@ class Oracle:
         pb.n_threads = int(n_threads or min(16, os.cpu_count() or 1))
         pb.unfold, pb.mode = unfold, mode
         pb.n_spans = int(getattr(fibre, "n_spans", 1))
+        pb.rolloff = float(getattr(fibre, "rolloff", 0.0))
+        pb.nli_points = int(getattr(fibre, "nli_points", 1))
         self.pb = pb
         self.n = len(f)
 
@@ -201,6 +209,15 @@ class Oracle:
         assert rc == 0, "oracle rejected the problem or a pair"
         return out
 
+    def tiles_at(self, f, intf) -> np.ndarray:
+        """tile(f[q], intf[q]) at arbitrary NLI frequencies f (no 16/27 gamma^2 factor)."""
+        f = _arr(f)
+        ki = np.ascontiguousarray(np.asarray(intf, dtype=np.int32))
+        assert f.shape == ki.shape
+        out = np.zeros(len(f))
+        assert lib().orc_tiles_at(C.byref(self.pb), len(f), _ptr(f), ki.ctypes.data_as(_ip), _ptr(out)) == 0
+        return out
+
     def psi(self, i: int, x, y) -> np.ndarray:
         x, y = _arr(x), _arr(y)
         out = np.zeros(len(x))
@@ -211,6 +228,26 @@ class Oracle:
         out = np.zeros(4)
         assert lib().orc_paper_quadrants(C.byref(self.pb), i, _ptr(out)) == 0
         return out
+
+    def paper_quadrants_at(self, f: float) -> np.ndarray:
+        """The paper's quadrants at NLI frequency f (no tiles); their sum times 16/27 gamma(f)^2 is G(f)."""
+        out = np.zeros(4)
+        assert lib().orc_paper_quadrants_at(C.byref(self.pb), float(f), _ptr(out)) == 0
+        return out
+
+    def nli_points(self, c: int):
+        """Points (Hz) and weights (Hz) of channel c's within-channel NLI rule."""
+        n = self.pb.nli_points
+        f, q = np.zeros(n), np.zeros(n)
+        assert lib().orc_nli_points(C.byref(self.pb), int(c), _ptr(f), _ptr(q)) == 0
+        return f, q
+
+    def psd(self, c: int, F):
+        """Transmit PSD of channel c at frequencies F (W/Hz), and gamma at F."""
+        F = _arr(F)
+        out, g = np.zeros(len(F)), np.zeros(len(F))
+        assert lib().orc_psd(C.byref(self.pb), int(c), len(F), _ptr(F), _ptr(out), _ptr(g)) == 0
+        return out, g
 
     def gamma(self) -> np.ndarray:
         out = np.zeros(self.n)
@@ -226,6 +263,10 @@ def steps(alpha_bar: float, L: float, n: int):
     edge, zm, dz = np.zeros(n + 1), np.zeros(n), np.zeros(n)
     assert lib().orc_steps(alpha_bar, L, n, _ptr(edge), _ptr(zm), _ptr(dz)) == 0
     return edge, zm, dz
+
+
+def spectrum_laplace(a: float, R: float, beta: float) -> float:
+    return lib().orc_spectrum_laplace(float(a), float(R), float(beta))
 
 
 def beta_from_dispersion(lam, D, S, Sdot):

@@ -64,6 +64,8 @@ class Fibre:
     ode_sub: int = 2
     precision: int = FP32
     n_spans: int = 1                   # identical spans, each followed by an amplifier
+    rolloff: float = 0.0               # raised-cosine roll-off of the transmit spectra (0: rectangular)
+    nli_points: int = 1                # points of the within-channel NLI rule (1: locally white)
 
     def replace(self, **kw) -> "Fibre":
         return dataclasses.replace(self, **kw)

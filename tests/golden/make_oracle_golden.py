@@ -38,11 +38,18 @@ from paper_2401_18022_amd import workloads as W  # noqa: E402
 BATCH_PROFILES = [int(round(x)) for x in np.linspace(0, 255, 16)]
 
 
+# fibre fields that switch model extensions on: hashed only when on, so a workload's hash does not
+# depend on extensions it does not use
+EXTENSION_DEFAULTS = {"rolloff": 0.0, "nli_points": 1}
+
+
 def inputs_sha256(wl) -> str:
     """Hash of everything the oracle reads: fibre fields and plan arrays."""
     h = hashlib.sha256()
     for f in dataclasses.fields(wl.fibre):
         v = getattr(wl.fibre, f.name)
+        if f.name in EXTENSION_DEFAULTS and v == EXTENSION_DEFAULTS[f.name]:
+            continue
         h.update(f.name.encode())
         h.update(np.ascontiguousarray(np.asarray(v, dtype=np.float64)).tobytes())
     p = wl.plan

@@ -57,10 +57,11 @@ def y_integral(x, lo, hi, b2, b3):
     return sum(integrate.quad(f, a, b, limit=5000, epsabs=0, epsrel=1e-10)[0] for a, b in zip(cuts[:-1], cuts[1:]))
 
 
-def brute_tile(centres, widths, psd, i, k, b2, b3):
+def brute_tile(centres, widths, psd, i, k, b2, b3, fi=None):
     """Cartesian brute force of tile(i,k): sum over channel blocks (c1, c2) of
-    int int_{f1 in c1, f2 in c2, f1+f2-f_i in k} G1 G2 Gk |link|^2, Gauss-Legendre outside, adaptive inside."""
-    fi = centres[i]
+    int int_{f1 in c1, f2 in c2, f1+f2-f_i in k} G1 G2 Gk |link|^2, Gauss-Legendre outside, adaptive inside.
+    fi: the NLI frequency (default: the centre of channel i)."""
+    fi = centres[i] if fi is None else fi
     slo, shi = centres[k] - fi - widths[k] / 2, centres[k] - fi + widths[k] / 2
     xs, ws = np.polynomial.legendre.leggauss(64)
     tot = 0.0
@@ -631,3 +632,237 @@ def test_raman_cutoff_separates_groups_and_switches_at_the_cutoff():
             assert pr["ell"][-1, 0] - plain[-1] > 1e-3 and pr["ell"][-1, 1] - plain[-1] < -1e-3
         else:
             np.testing.assert_allclose(pr["ell"], plain[:, None] * np.ones((1, 2)), rtol=1e-13)
+
+
+# ----------------------------------------------------------------------------- raised-cosine spectra
+# The transmit PSD of a channel is P_c times a unit-area raised-cosine shape of roll-off beta (the
+# PSD of an RRC-filtered signal; beta = 0 is the paper's rectangle), and the NLI power of a COI is
+# its NLI PSD integrated against the receiver's power response R_i g_i over the band, by a
+# normalised midpoint rule whose one-point form is the locally-white R_i G(f_i).
+
+def _rc_problem(beta, p_w=1e-3, n=1, spacing=150e9, **fib):
+    f = W.F_1550 + spacing * (np.arange(n) - (n - 1) / 2)
+    plan = W.single_plan(f, R, p_w, 1.0)
+    fib.setdefault("cr_per_w_m_hz", 0.0)
+    return O.Oracle(W.tiny_fibre(rolloff=beta, **fib), plan)
+
+
+@pytest.mark.parametrize("beta", [0.0, 0.01, 0.35, 1.0])
+def test_raised_cosine_psd_integrates_to_the_power(beta):
+    """The PSD integrates to P over its support (1+beta) R, is P/R in its flat part, passes P/(2R) at
+    +-R/2 and is vestigially symmetric about +-R/2 (g(R/2 - x) + g(R/2 + x) = 1/R), zero beyond."""
+    o = _rc_problem(beta, p_w=2e-3)
+    fc = o.plan.f_hz[0]
+    edges = sorted({-(1 + beta) * R / 2, -(1 - beta) * R / 2, 0.0, (1 - beta) * R / 2, (1 + beta) * R / 2})
+    tot = 0.0
+    for a, b in zip(edges[:-1], edges[1:]):
+        if b > a:
+            tot += integrate.quad(lambda u: o.psd(0, [fc + u])[0][0], a, b, epsabs=0, epsrel=1e-13)[0]
+    assert tot == pytest.approx(2e-3, rel=1e-11)
+    if beta > 0:  # (the rectangle jumps at +-R/2)
+        half = o.psd(0, [fc - R / 2, fc + R / 2])[0]
+        np.testing.assert_allclose(half, 2e-3 / (2 * R), rtol=1e-12)
+        x = np.linspace(0, beta * R / 2, 7)
+        lo, hi = o.psd(0, fc + R / 2 - x)[0], o.psd(0, fc + R / 2 + x)[0]
+        np.testing.assert_allclose(lo + hi, 2e-3 / R, rtol=1e-12)
+    assert np.all(o.psd(0, fc + np.array([-1, 1]) * (1 + beta) * R / 2 * 1.000001)[0] == 0.0)
+    assert o.psd(0, [fc + 0.999 * (1 - beta) * R / 2])[0][0] == pytest.approx(2e-3 / R, rel=1e-14)
+
+
+def test_raised_cosine_is_a_rectangle_convolved_with_a_half_cosine():
+    """The shape equals (1/R) rect_R convolved with the unit half-cosine lobe of width beta R,
+    computed by direct numerical convolution."""
+    beta = 0.4
+    o = _rc_problem(beta)
+    fc = o.plan.f_hz[0]
+    h = beta * R / 2
+    lobe = lambda v: math.pi / (4 * h) * math.cos(math.pi * v / (2 * h))   # unit area on |v| <= h
+    for u in (0.0, 0.3 * R, 0.45 * R, 0.5 * R, 0.62 * R, 0.69 * R):
+        ref = integrate.quad(lambda v: lobe(v) * (1.0 if abs(u - v) < R / 2 else 0.0) / R, -h, h,
+                             points=[u - R / 2, u + R / 2], epsabs=0, epsrel=1e-12)[0]
+        assert o.psd(0, [fc + u])[0][0] / 1e-3 == pytest.approx(ref, rel=1e-9, abs=1e-25)
+
+
+@pytest.mark.parametrize("beta", [0.0, 0.01, 0.5, 1.0])
+def test_spectrum_transform_of_the_closed_form_profile(beta):
+    """M(a) = int g(u) exp(-a u) du of the unit raised cosine (the closed-form profile's normaliser
+    term) against numerical quadrature; beta = 0 is sinhc(a R / 2)."""
+    for a in (1e-13, 1e-12, 1e-11, 5e-11):
+        o = _rc_problem(beta)
+        fc = o.plan.f_hz[0]
+        g = lambda u: o.psd(0, [fc + u])[0][0] / 1e-3 * math.exp(-a * u)
+        edges = sorted({-(1 + beta) * R / 2, -(1 - beta) * R / 2, (1 - beta) * R / 2, (1 + beta) * R / 2})
+        ref = sum(integrate.quad(g, lo, hi, epsabs=0, epsrel=1e-13)[0] for lo, hi in zip(edges[:-1], edges[1:]) if hi > lo)
+        assert O.spectrum_laplace(a, R, beta) == pytest.approx(ref, rel=1e-10), (a, beta)
+    x = 1e-11 * R / 2
+    assert O.spectrum_laplace(1e-11, R, 0.0) == pytest.approx(math.sinh(x) / x, rel=1e-14)
+
+
+def test_closed_form_profile_conserves_power_with_raised_cosine_spectra():
+    """P1 with raised-cosine spectra: sum_k int P_k g_k(f) rho(z, f) df = P_tot exp(-alpha z) at every step
+    (the normaliser uses the spectra's transforms M_k(a))."""
+    beta = 0.5
+    f = W.F_1550 + 150e9 * (np.arange(5) - 2.0)
+    plan = W.single_plan(f, R, 30e-3 * np.array([1.0, 0.5, 2.0, 1.5, 0.7]), 1.0)
+    o = O.Oracle(W.tiny_fibre(rolloff=beta, n_steps=12), plan)
+    pr = o.profile()
+    xs, ws = np.polynomial.legendre.leggauss(40)
+    for m in (0, 5, 11):
+        tot = 0.0
+        for c in range(5):
+            edges = f[c] + np.array([-(1 + beta), -(1 - beta), 1 - beta, 1 + beta]) * R / 2
+            for a, b in zip(edges[:-1], edges[1:]):
+                F = 0.5 * (a + b) + 0.5 * (b - a) * xs
+                tot += 0.5 * (b - a) * np.sum(ws * o.psd(c, F)[0] * np.exp(o.lnrho(np.full(len(F), m), F)))
+        assert tot == pytest.approx(plan.p_w.sum() * math.exp(-ALPHA * pr["zm"][m]), rel=1e-10), m
+
+
+def test_rolloff_to_zero_reproduces_the_rectangle():
+    wl = W.random_small(5, seed=31, profile=W.PROFILE_CLOSED_FORM, grid_s=16, grid_v=16, n_steps=16)
+    base = O.Oracle(wl.fibre, wl.plan).forward()
+    for beta, tol in ((1e-9, 1e-7), (1e-6, 1e-4)):
+        r = O.Oracle(wl.fibre.replace(rolloff=beta), wl.plan).forward()
+        np.testing.assert_allclose(r["eta"], base["eta"], rtol=tol)
+    r = O.Oracle(wl.fibre.replace(rolloff=0.02), wl.plan).forward()
+    assert np.max(np.abs(r["eta"] / base["eta"] - 1)) > 1e-5   # the shape does enter
+
+
+# ----------------------------------------------------------------------------- within-channel NLI
+
+def _sci_width(u, a, b):
+    """upsilon2-width of {x, y, x + y in [a, b)} (a < 0 < b) at |x y| = u, over all four quadrants:
+    Q1 2 acosh(b / 2r), Q3 2 acosh(|a| / 2r), Q2 = Q4 the v-interval of x < b, y >= a, x + y in [a, b)."""
+    r = math.sqrt(u)
+    w = 0.0
+    if b > 2 * r:
+        w += 2 * math.acosh(b / (2 * r))
+    if -a > 2 * r:
+        w += 2 * math.acosh(-a / (2 * r))
+    w4 = min(math.log(b / r), math.asinh(b / (2 * r))) - max(math.log(r / -a), math.asinh(a / (2 * r)))
+    return w + 2 * max(w4, 0.0)
+
+
+def _sci_tile_reference(delta):
+    """tile at NLI frequency f_c + delta of one rectangular channel (no Raman, beta3 = beta4 = 0): the
+    integrand depends on x y only, so tile = (P/R)^3 int W(u) |link(u)|^2 du with the width above."""
+    a, b = -R / 2 - delta, R / 2 - delta
+    f = lambda s: _sci_width(math.exp(s), a, b) * exact_link2(-4 * math.pi ** 2 * B2 * math.exp(s)) * math.exp(s)
+    smax = math.log(max(b, -a) ** 2 / 4 * 4)
+    pts = sorted({math.log(b * b / 4), math.log(a * a / 4), math.log(ALPHA / (4 * math.pi ** 2 * abs(B2)))})
+    val, _ = integrate.quad(f, smax - 30 * math.log(10), smax, points=pts, limit=800, epsabs=0, epsrel=1e-12)
+    return (1e-3 / R) ** 3 * val
+
+
+def test_off_centre_sci_tile_reduces_to_one_dimensional_integral():
+    """The SCI tile at NLI frequencies away from the channel centre (the within-channel rule's points)."""
+    wl = W.single_channel(grid_s=1024, grid_v=2, n_steps=1000, beta3=0.0)
+    o = O.Oracle(wl.fibre, wl.plan)
+    deltas = np.array([0.0, 0.2 * R, -0.35 * R, 0.45 * R])
+    got = o.tiles_at(wl.plan.f_hz[0] + deltas, [0] * len(deltas))
+    ref = [_sci_tile_reference(d) for d in deltas]
+    np.testing.assert_allclose(got, ref, rtol=3e-5)
+    assert got[0] == pytest.approx(o.forward()["tiles"][0, 0], rel=1e-14)
+
+
+def test_within_channel_nli_of_one_channel():
+    """P_NLI with n points = 16/27 gamma^2 sum_j (R/n) tile(f_c + delta_j) at the n sub-band midpoints
+    (the 1-D references), and converges to 16/27 gamma^2 int_band G df as n grows.  The single-channel
+    NLI PSD falls to about a third of its centre value at the band edges, so the locally-white value
+    is 16 % high and the midpoint rule converges at about O(n^-1.4)."""
+    warnings.simplefilter("ignore", integrate.IntegrationWarning)
+    wl = W.single_channel(grid_s=1024, grid_v=2, n_steps=1000, beta3=0.0)
+    full = integrate.quad(_sci_tile_reference, -R / 2, R / 2, epsabs=0, epsrel=1e-9, limit=200)[0]
+    full_pnli = 16 / 27 * GAMMA ** 2 * full
+    errs = []
+    for n in (1, 2, 4, 8, 16):
+        r = O.Oracle(wl.fibre.replace(nli_points=n), wl.plan).forward()
+        deltas = (np.arange(n) + 0.5) * R / n - R / 2
+        ref = 16 / 27 * GAMMA ** 2 * sum(R / n * _sci_tile_reference(d) for d in deltas)
+        assert r["pnli"][0] == pytest.approx(ref, rel=3e-5), n
+        errs.append(abs(r["pnli"][0] / full_pnli - 1))
+    assert 0.15 < errs[0] < 0.17              # the locally-white value is off by a visible amount
+    assert all(a / b > 2 for a, b in zip(errs[:-1], errs[1:])) and errs[-1] < 5e-3
+
+
+def test_off_centre_xci_tiles_match_brute_force():
+    """Off-centre XCI tiles (two channels 0.2 THz apart) against Cartesian brute force."""
+    warnings.simplefilter("ignore", integrate.IntegrationWarning)
+    wl = W.two_channel(0.2e12, grid_s=256, grid_v=256, n_steps=1000, beta3=0.0)
+    o = O.Oracle(wl.fibre, wl.plan)
+    c = wl.plan.f_hz - wl.plan.f_hz[0]
+    psd = wl.plan.p_w / wl.plan.rs_hz
+    for d in (0.3 * R, -0.4 * R):
+        got = o.tiles_at([wl.plan.f_hz[0] + d], [1])[0]
+        ref = brute_tile(c, wl.plan.rs_hz, psd, 0, 1, B2, 0.0, fi=d)
+        assert got == pytest.approx(ref, rel=1e-3), d
+
+
+def test_raised_cosine_tiles_cover_their_strips_at_off_centre_frequencies():
+    """Unit integrand: every tile at an off-centre NLI frequency integrates the strip x + y in channel
+    k's support (1+beta) R of the band square, whose edges are the outer channels' support edges."""
+    beta = 0.3
+    f = W.F_1550 + 150e9 * (np.arange(4) - 1.5)
+    plan = W.single_plan(f, R, 1e-3, 1.0)
+    o = O.Oracle(W.tiny_fibre(rolloff=beta, grid_s=4096, grid_v=2, n_steps=2), plan, mode=1)
+    hw = (1 + beta) * R / 2
+    for i, d in ((0, -0.4 * R), (2, 0.35 * R)):
+        fi = f[i] + d
+        t = o.tiles_at([fi] * 4, range(4))
+        xp, xn = f[-1] + hw - fi, fi - (f[0] - hw)
+        for k in range(4):
+            ref = strip_area(xn, xp, f[k] - fi - hw, f[k] - fi + hw)
+            assert t[k] == pytest.approx(ref, rel=1e-4), (i, k)
+
+
+def test_within_channel_rule_points_and_weights():
+    """n midpoints across the support, symmetric, weights proportional to the receiver response and
+    summing to the noise bandwidth R (a flat NLI PSD is integrated exactly); one point: the centre
+    with weight R."""
+    for beta in (0.0, 0.2):
+        for n in (1, 4, 7):
+            o = _rc_problem(beta, nli_points=n)
+            fc = o.plan.f_hz[0]
+            f, q = o.nli_points(0)
+            d = (1 + beta) * R / n
+            np.testing.assert_allclose(f - fc, -(1 + beta) * R / 2 + (np.arange(n) + 0.5) * d, rtol=0, atol=0.1)
+            np.testing.assert_allclose(f - fc, -(f - fc)[::-1], atol=0.1)
+            assert q.sum() == pytest.approx(R, rel=1e-14)
+            resp = o.psd(0, f)[0] / 1e-3 * R
+            np.testing.assert_allclose(q / q.sum(), resp / resp.sum(), rtol=1e-13)
+    f, q = _rc_problem(0.3, nli_points=1).nli_points(0)
+    assert f[0] == W.F_1550 and q[0] == pytest.approx(R, rel=1e-15)
+
+
+def test_within_channel_weights_carry_gamma_of_each_point():
+    """With gamma(f) from n2 and A_eff(f), each point's tiles are weighted by gamma(f_j)^2: doubling n2
+    quadruples P_NLI, and a frequency-dependent A_eff makes the n-point result differ from a constant
+    gamma at the centre only through gamma(f_j)^2 / gamma(f_i)^2."""
+    wl = W.random_small(4, seed=41, grid_s=12, grid_v=12, n_steps=12)
+    fb = wl.fibre.replace(nli_points=3, gamma_const_per_w_m=0.0)
+    o = O.Oracle(fb, wl.plan)
+    r = o.forward(coi=[1])
+    r2 = O.Oracle(fb.replace(n2_m2_per_w=2 * fb.n2_m2_per_w), wl.plan).forward(coi=[1])
+    assert r2["pnli"][0] == pytest.approx(4 * r["pnli"][0], rel=1e-12)
+    f, q = o.nli_points(1)
+    _, g = o.psd(1, f)
+    gi = o.gamma()[1]
+    tiles = np.array([o.tiles_at([fj] * 4, range(4)).sum() for fj in f])
+    ref = 16 / 27 * np.sum(q * g ** 2 * tiles)
+    assert r["pnli"][0] == pytest.approx(ref, rel=1e-12)
+    assert abs(g[0] / gi - 1) > 1e-4                 # gamma does vary across the band
+
+
+@pytest.mark.parametrize("beta,n", [(0.0, 3), (0.3, 2)])
+def test_within_channel_and_raised_cosine_duals_match_central_differences(beta, n):
+    wl = W.random_small(4, seed=43, grid_s=10, grid_v=10, n_steps=10)
+    fb = wl.fibre.replace(rolloff=beta, nli_points=n)
+    f = wl.plan.f_hz[0] + 200e9 * np.arange(4)
+    plan = W.single_plan(f, R, wl.plan.p_w * 30, 1.0)
+    o = O.Oracle(fb, plan)
+    d = np.random.default_rng(2).normal(size=4) * plan.p_w
+    r = o.forward_dual(d)
+    h = 1e-5
+    tp = O.Oracle(fb, plan.with_power(plan.p_w + h * d)).forward()
+    tm = O.Oracle(fb, plan.with_power(plan.p_w - h * d)).forward()
+    assert r["dthr"] == pytest.approx((tp["thr"] - tm["thr"]) / (2 * h), rel=1e-6)
+    np.testing.assert_allclose(r["dsnr"], (tp["snr"] - tm["snr"]) / (2 * h), rtol=1e-6)
