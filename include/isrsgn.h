@@ -24,7 +24,16 @@
  *   * distance steps: n_steps steps with equal power decrement under the mean
  *     loss of the occupied channels, the power term evaluated at the midpoints;
  *   * ln rho(z, f) is interpolated linearly in f between channel centres;
- *   * P_NLI,i = 16/27 gamma_i^2 R_i sum_k tile(i,k); eta_i = P_NLI,i / P_i^3;
+ *   * transmit spectra (eq. new_gn_model's G_Tx): P_c times a unit-area raised cosine of roll-off
+ *     beta (the PSD of an RRC-filtered signal), flat to (1-beta) R_c/2 and zero from (1+beta) R_c/2;
+ *     beta = 0 (the default) is the rectangle of width R_c;
+ *   * noise powers are noise PSDs integrated against the receiver's power response R_i g_i(f - f_i)
+ *     (unit passband, noise bandwidth R_i).  For the NLI, nli_points midpoints of equal parts of
+ *     the COI's support, weights proportional to the response and normalised to R_i, each point f_j
+ *     with its own tiles (i, j, k) (NLI frequency f_j in place of f_i in the offsets, the phase and
+ *     the f term of eq. pk) and gamma(f_j)^2; one point (the default) is the locally-white R_i G(f_i);
+ *   * P_NLI,i = 16/27 gamma_i^2 R_i sum_k tile(i,k), tile(i,k) = sum_j w_j tile(i,j,k),
+ *     w_j = q_j gamma(f_j)^2 / (gamma_i^2 R_i) (w = 1 with one point); eta_i = P_NLI,i / P_i^3;
  *     P_ASE,i = NF_i h f_i R_i / rho(L, f_i);  SNR_i = P_i / (P_NLI,i + P_ASE,i)
  *     (combined with a transceiver SNR as 1/(1/SNR + 1/SNR_trx) when given);
  *     T = sum over P_i > 0 of 2 R_i log2(1 + SNR_i).
@@ -103,11 +112,16 @@ typedef struct {
                              * power (App. A, eq. gain summed over spans), 1..100000: every node's
                              * |S|^2 carries the phased-array factor sin^2(n phi L/2)/sin^2(phi L/2)
                              * and the ASE is n times one span's */
+  double rolloff;           /* raised-cosine roll-off of every transmit spectrum, 0..1 (0: rectangular);
+                             * the closed-form profile then uses the spectrum's Laplace transform
+                             * sinhc(aR/2) cosh(a beta R/2) / (1 + (a beta R/pi)^2) for sinhc(aR/2) */
+  int nli_points;           /* points of the within-channel NLI rule, 1..64 (1: locally white); the
+                             * pair-integral work grows in proportion */
 } isrsgn_fibre_desc;
 
 /* One or more channel plans, concatenated CSR-style (host memory).
  * Plan b owns channels [ch_offsets[b], ch_offsets[b+1]); each plan is sorted by
- * frequency with non-overlapping rectangular channels (f_{k+1} - f_k >= (R_k + R_{k+1})/2),
+ * frequency with non-overlapping spectra (f_{k+1} - f_k >= (1 + rolloff) (R_k + R_{k+1})/2),
  * 1..1024 channels.  Device copies are cached by content. */
 typedef struct {
   int n_batch;
@@ -125,7 +139,9 @@ int isrsgn_setup_fibre(const isrsgn_fibre_desc* desc, isrsgn_fibre** out);
  *   eta_dev[n_ch_total]     eta_i = P_NLI,i / P_i^3 (NaN where P_i == 0)
  *   pnli_w_dev[n_ch_total]  P_NLI,i in W (may be NULL)
  *   tile_dev_or_null        per plan an N_b x N_b row-major block [i][k] of tile integrals
- *                           (W^3/Hz^3 * Hz^2 * m^2), blocks concatenated in plan order; may be NULL */
+ *                           (W^3/Hz^3 * Hz^2 * m^2; with several NLI points the weighted sum over
+ *                           them, so P_NLI,i = 16/27 gamma_i^2 R_i sum_k tile(i,k) holds), blocks
+ *                           concatenated in plan order; may be NULL */
 int isrsgn_eta(isrsgn_fibre* h, const isrsgn_plan* plan, const double* P_w_dev, double* eta_dev,
                double* pnli_w_dev, double* tile_dev_or_null, void* hip_stream);
 

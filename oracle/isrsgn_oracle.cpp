@@ -456,7 +456,7 @@ void nli_points(const Channels& ch, int i, int n, std::vector<double>* f, std::v
   const double d = 2.0 * ch.half(i) / n;
   double sum = 0.0;
   for (int j = 0; j < n; ++j) {
-    (*f)[j] = ch.f[i] - ch.half(i) + (j + 0.5) * d;
+    (*f)[j] = ch.f[i] + (j + 0.5 - 0.5 * n) * d;
     (*q)[j] = ch.R[i] * ch.shape(i, (*f)[j]);
     sum += (*q)[j];
   }

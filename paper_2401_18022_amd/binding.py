@@ -39,7 +39,7 @@ class FibreDesc(C.Structure):
         ("cr_per_w_m_hz", C.c_double), ("aeff_ref_m2", C.c_double), ("raman_cutoff_hz", C.c_double),
         ("profile", C.c_int), ("photon_ratio", C.c_int), ("n_steps", C.c_int),
         ("grid_s", C.c_int), ("grid_v", C.c_int), ("s_decades", C.c_double), ("ode_sub", C.c_int),
-        ("precision", C.c_int), ("n_spans", C.c_int),
+        ("precision", C.c_int), ("n_spans", C.c_int), ("rolloff", C.c_double), ("nli_points", C.c_int),
     ]
 
 
@@ -108,6 +108,8 @@ def make_desc(fibre: W.Fibre, precision: Optional[int] = None):
     d.s_decades, d.ode_sub = fibre.s_decades, fibre.ode_sub
     d.precision = fibre.precision if precision is None else precision
     d.n_spans = fibre.n_spans
+    d.rolloff = float(getattr(fibre, "rolloff", 0.0))
+    d.nli_points = int(getattr(fibre, "nli_points", 1))
     return d, keep
 
 

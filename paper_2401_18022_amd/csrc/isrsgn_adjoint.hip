@@ -87,7 +87,7 @@ __host__ __device__ inline size_t adjoint_lds_bytes(int nmax, int gs, int M, int
   const int mc = prec == 0 ? 16 : 8;
   const size_t rb = prec == 0 ? 4 : 8;
   // (+1 double: the step tables start on a 16-byte boundary)
-  return sizeof(double) * (4 * (size_t)nmax + 4 * (size_t)gs + (size_t)nmax + 6 * (size_t)M + 8 + 1) +
+  return sizeof(double) * (4 * (size_t)nmax + 4 * (size_t)gs + (size_t)nmax + 7 * (size_t)M + 8 + 1) +
          (sizeof(StepLds) + sizeof(Col4)) * (size_t)M + adj_waves(prec) * (size_t)mc * stage_row(prec) * rb +
          adj_waves(prec) * 7 * kMetaStride * 4 + 16;
 }
@@ -163,7 +163,8 @@ struct AdjArgs {
 
 // kStored: S of every node comes from w.s_store, written by the forward tile kernel for the
 // same row batch, instead of a recomputing sweep over the steps.
-template <int kPrec, bool kLinear, bool kStored>
+// kRc: raised-cosine spectra (node shapes in the G products; a separate instantiation)
+template <int kPrec, bool kLinear, bool kStored, bool kRc>
 __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
   constexpr int kAdjWaves = adj_waves(kPrec), kAdjBlock = 64 * kAdjWaves;
   using real = typename AdjCfg<kPrec>::real;
@@ -179,8 +180,8 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
   d += 4 * GS;
   double* gGl = d;
   d += nmax;
-  double* tacc = d;  // [6][M]: the tile's hot channels k-1, k, k+1, i-1, i, i+1
-  d += 6 * M;
+  double* tacc = d;  // [7][M]: the tile's hot channels k-1, k, k+1, i-1, i, i+1; row 6: the f term
+  d += 7 * M;
   double* red = d;
   d += 8;
   d += (d - reinterpret_cast<double*>(smem_raw)) & 1;  // 16-byte boundary for the step tables
@@ -203,24 +204,34 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
     __syncthreads();
     const unsigned int t = *tile_slot;
     if (t >= A.t_end) break;
-    int b, i, k;
-    decode_tile(pv, t, &b, &i, &k);
+    int b, i, j, k;
+    decode_tile(pv, t, &b, &i, &j, &k);
     const int o = pv.off[b], n = pv.off[b + 1] - o;
-    const double lam = A.w.lam[o + i];
+    // the tile's upstream weight: the COI's lambda times the weight of its point in the tile row
+    const double lam = A.w.lam[o + i] * pv.wpt[(size_t)(o + i) * pv.nli + j];
+    const double fnli = pv.fpt[(size_t)(o + i) * pv.nli + j];
+    int sf;
+    double tf;
+    nli_segment(pv.f + o, n, i, fnli, &sf, &tf);
+    sf = __builtin_amdgcn_readfirstlane(sf);  // tile-uniform: scalar registers
+    tf = uniform_f64(tf);
     if (lam == 0.0) {  // COI outside the throughput (an empty channel): nothing flows back
       __syncthreads();
       continue;
     }
     if (b != cur_b) {
-      load_channels(ch, pv, A.P, o, n);
+      load_channels(ch, pv, A.P, o, n, A.fp.rolloff);
       if (kPrec == 0) load_steps(steps, A.w.zm + (size_t)b * M, A.w.dz + (size_t)b * M, A.w.hdz32 + (size_t)b * M, M);
       cur_b = b;
     }
-    if (kPrec == 0) load_cols<kLinear>(col, A.w.lt32 + (size_t)M * o, n, M, i, k);
+    if (kPrec == 0) load_cols<kLinear>(col, A.w.lt32 + (size_t)M * o, n, M, sf, tf, k);
+    // FP64 form: the f-term column in the step-table slot (unused by that form)
+    double* lf64 = reinterpret_cast<double*>(steps);
+    if (kPrec == 1 && !kLinear) load_fcol64(lf64, A.w.ell64 + (size_t)M * o, n, M, sf, tf);
     for (int c = tid; c < n; c += kAdjBlock) gGl[c] = 0.0;
-    for (int q = tid; q < 6 * M; q += kAdjBlock) tacc[q] = 0.0;
+    for (int q = tid; q < 7 * M; q += kAdjBlock) tacc[q] = 0.0;
     __syncthreads();
-    const TileGeo g = uniform_geo(tile_geo(ch, n, i, k, A.fp.f_ref));
+    const TileGeo g = uniform_geo(tile_geo(ch, n, fnli, k, A.fp.f_ref));
     const double* zm = A.w.zm + (size_t)b * M;
     const double* dz = A.w.dz + (size_t)b * M;
     const float* hdz = A.w.hdz32 + (size_t)b * M;
@@ -237,8 +248,12 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
         const int64_t q = base + tid;
         Node nd;
         const bool valid = q < nodes && make_node(ch, rw, g, n, k, part, (int)(q / GV), (int)(q % GV), A.fp, &nd);
+        // raised-cosine shapes at f1, f2, f3 relative to the flat PSDs (1: rectangle)
+        double sh1 = 1.0, sh2 = 1.0, sh3 = 1.0;
+        if (kRc && valid)
+          node_shapes(ch, rw, g, k, part, (int)(q / GV), (int)(q % GV), nd.c1, nd.c2, A.fp.rolloff, &sh1, &sh2, &sh3);
         // per-node values used after pass 1 (taken now: the node's other fields die here)
-        const real cq = valid ? (real)(lam * nd.w * nd.gprod) : (real)0;
+        const real cq = valid ? (real)(lam * nd.w * nd.gprod * (sh1 * sh2 * sh3)) : (real)0;
         const double lw = valid ? lam * nd.w : 0.0;
         const int c1 = valid ? nd.c1 : 0, c2 = valid ? nd.c2 : 0;
         const float wgt = kLinear ? 2.0f : 1.0f;
@@ -304,26 +319,33 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
               sr = sv.x;
               si = sv.y;
             }
-            if (kPrec == 1) t64 = term64_setup(nd, i);
+            if (kPrec == 1) t64 = term64_setup(nd);
           } else if (kPrec == 0) {
             float a32, b32;
             accumulate32<kLinear, 4>(t32, sp, steps, col, gsrc, M, &a32, &b32);
             sr = a32;
             si = b32;
           } else {
-            t64 = term64_setup(nd, i);
+            t64 = term64_setup(nd);
             const double* tab = A.w.ell64 + (size_t)M * o;
             for (int m = 0; m < M; ++m) {
-              const double2 a = term64<kLinear>(t64, m, zm, dz, tab, n);
+              const double2 a = term64<kLinear>(t64, m, zm, dz, tab, n, lf64);
               sr += a.x;
               si += a.y;
             }
           }
           const double s2 = (double)sr * sr + (double)si * si;
           const double base2 = lw * s2, p1 = ch.psd[c1], p2 = ch.psd[c2];
-          atomicAdd(&gGl[c1], base2 * p2 * g.gk);
-          atomicAdd(&gGl[c2], base2 * p1 * g.gk);
-          gk_acc += base2 * p1 * p2;
+          if constexpr (kRc) {  // dG(f)/dP_c = shape / R_c: the shape of the differentiated factor
+            const double g1 = p1 * sh1, g2 = p2 * sh2, g3 = g.gk * sh3;
+            atomicAdd(&gGl[c1], base2 * sh1 * g2 * g3);
+            atomicAdd(&gGl[c2], base2 * sh2 * g1 * g3);
+            gk_acc += base2 * g1 * g2 * sh3;
+          } else {
+            atomicAdd(&gGl[c1], base2 * p2 * g.gk);
+            atomicAdd(&gGl[c2], base2 * p1 * g.gk);
+            gk_acc += base2 * p1 * p2;
+          }
         }
         real* my_stage = stage + (size_t)wv * MC * kRow;
         // pass 2 in chunks of MC steps
@@ -336,7 +358,7 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
               const int m = m0 + mm;
               real qv = 0;
               if (valid && m < M) {
-                const double2 a = term64<kLinear>(t64, m, zm, dz, A.w.ell64 + (size_t)M * o, n);
+                const double2 a = term64<kLinear>(t64, m, zm, dz, A.w.ell64 + (size_t)M * o, n, lf64);
                 qv = (real)(cq * (sr * a.x + si * a.y));
               }
               my_stage[mm * kRow + lane] = qv;
@@ -463,7 +485,7 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
               atomicAdd(&tacc[0 * M + m], (double)x3a);
               atomicAdd(&tacc[1 * M + m], (double)((real)wgt * qs - x3a - x3c));
               atomicAdd(&tacc[2 * M + m], (double)x3c);
-              if (!kLinear) atomicAdd(&tacc[4 * M + m], -(double)qs);
+              if (!kLinear) atomicAdd(&tacc[6 * M + m], -(double)qs);  // the f term (row 6)
             }
           }
           __syncwarp();  // the next chunk overwrites this wave's staging
@@ -474,6 +496,16 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
     // tile end: flush the per-tile accumulators
     gk_acc = block_sum(gk_acc, red);
     if (tid == 0) gGl[k] += gk_acc;
+    // the f term to the NLI frequency's segment (sf, sf + 1), both among the COI's hot rows
+    for (int m = tid; m < M && !kLinear; m += kAdjBlock) {
+      const double v = tacc[6 * M + m];
+      if (tf == 0.0) {
+        tacc[(sf - i + 4) * M + m] += v;
+      } else {
+        tacc[(sf - i + 4) * M + m] += (1.0 - tf) * v;
+        tacc[(sf - i + 5) * M + m] += tf * v;
+      }
+    }
     __syncthreads();
     for (int c = tid; c < n; c += kAdjBlock)
       if (gGl[c] != 0.0) atomicAdd(&A.w.gG[o + c], gGl[c]);
@@ -488,13 +520,16 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
 
 // ---------------------------------------------------------------------------- profile adjoint
 // Closed form: ln rho(z_m, f_c) = -alpha z_m - a_m (f_c - f_ref) - ln N_m with
-// a_m = P_tot C_r L_eff(z_m), N_m = sum_j (P_j/P_tot) E_j(a_m), E_j(a) = exp(-a d_j) sinhc(a R_j/2).
+// a_m = P_tot C_r L_eff(z_m), N_m = sum_j (P_j/P_tot) E_j(a_m), E_j(a) = exp(-a d_j) M_j(a) (M_j the
+// spectrum's transform: sinhc(a R_j/2) for the rectangle).
 // With A1_m = sum_c dT/dln rho(m,c) and A2_m = sum_c dT/dln rho(m,c) (f_c - f_ref):
 //   dT/dP_j += sum_m [ -A2_m C L_m - A1_m ((E_j(a_m)/N_m - 1)/P_tot + C L_m D_m / N_m) ],
 //   D_m = sum_j (P_j/P_tot) E_j'(a_m).  Row m == M is the span end.
-__device__ inline double Ej(double a, double dj, double Rj) { return exp(-a * dj) * sinhc(0.5 * a * Rj); }
-__device__ inline double Ejd(double a, double dj, double Rj) {
-  return exp(-a * dj) * (-dj * sinhc(0.5 * a * Rj) + 0.5 * Rj * sinhc_d(0.5 * a * Rj));
+__device__ inline double Ej(double a, double dj, double Rj, double beta) {
+  return exp(-a * dj) * spectrum_m(a, Rj, beta);
+}
+__device__ inline double Ejd(double a, double dj, double Rj, double beta) {
+  return exp(-a * dj) * (-dj * spectrum_m(a, Rj, beta) + spectrum_md(a, Rj, beta));
 }
 
 __global__ void k_cf_adj_rows(PlanView pv, FibreParams fp, const double* __restrict__ P, Work w, double* coef) {
@@ -519,8 +554,8 @@ __global__ void k_cf_adj_rows(PlanView pv, FibreParams fp, const double* __restr
     double sN = 0.0, sD = 0.0;
     for (int c = threadIdx.x; c < n; c += blockDim.x) {
       const double dj = pv.f[o + c] - fp.f_ref, Rj = pv.R[o + c], wj = P[o + c] / pt;
-      sN += wj * Ej(a, dj, Rj);
-      sD += wj * Ejd(a, dj, Rj);
+      sN += wj * Ej(a, dj, Rj, fp.rolloff);
+      sD += wj * Ejd(a, dj, Rj, fp.rolloff);
     }
     N = block_sum(sN, red);
     D = block_sum(sD, red);
@@ -541,7 +576,7 @@ __global__ void k_cf_adj_channels(PlanView pv, FibreParams fp, Work w, const dou
     const double* cf = coef + ((size_t)b * (M + 1) + m) * 8;
     const double a = cf[0], N = cf[1], D = cf[2], A1 = cf[3], A2 = cf[4], CL = cf[5], pt = cf[6];
     if (!(pt > 0.0)) continue;
-    acc += -A2 * CL - A1 * ((Ej(a, dj, Rj) / N - 1.0) / pt + CL * D / N);
+    acc += -A2 * CL - A1 * ((Ej(a, dj, Rj, fp.rolloff) / N - 1.0) / pt + CL * D / N);
   }
   w.gP[g] += acc;
 }
@@ -647,21 +682,25 @@ __global__ void k_grad_final(PlanView pv, Work w, double* dthr) {
 
 size_t adjoint_lds(int nmax, int gs, int M, int prec) { return adjoint_lds_bytes(nmax, gs, M, prec); }
 
+namespace {
+using AdjKernel = void (*)(AdjArgs);
+#define ISRSGN_ADJ(P, RC)                                                                          \
+  {{k_adjoint<P, false, false, RC>, k_adjoint<P, false, true, RC>},                                \
+   {k_adjoint<P, true, false, RC>, k_adjoint<P, true, true, RC>}}
+// [precision][raised cosine][linear profile][stored S]
+const AdjKernel kAdjKernels[2][2][2][2] = {{ISRSGN_ADJ(0, false), ISRSGN_ADJ(0, true)},
+                                           {ISRSGN_ADJ(1, false), ISRSGN_ADJ(1, true)}};
+
+const void* adjoint_kernel(const FibreParams& fp, bool stored) {
+  return reinterpret_cast<const void*>(
+      kAdjKernels[fp.precision ? 1 : 0][fp.rolloff > 0.0 ? 1 : 0][fp.profile == 0 ? 1 : 0][stored ? 1 : 0]);
+}
+}  // namespace
+
 int adjoint_blocks_per_cu(const FibreParams& fp, int nmax, bool stored) {
   int nb = 0;
   const size_t shm = adjoint_lds_bytes(nmax, fp.grid_s, fp.n_steps, fp.precision);
-  const void* k;
-  if (fp.precision == 0) {
-    if (stored) k = fp.profile == 0 ? reinterpret_cast<const void*>(k_adjoint<0, true, true>)
-                                    : reinterpret_cast<const void*>(k_adjoint<0, false, true>);
-    else k = fp.profile == 0 ? reinterpret_cast<const void*>(k_adjoint<0, true, false>)
-                             : reinterpret_cast<const void*>(k_adjoint<0, false, false>);
-  } else {
-    if (stored) k = fp.profile == 0 ? reinterpret_cast<const void*>(k_adjoint<1, true, true>)
-                                    : reinterpret_cast<const void*>(k_adjoint<1, false, true>);
-    else k = fp.profile == 0 ? reinterpret_cast<const void*>(k_adjoint<1, true, false>)
-                             : reinterpret_cast<const void*>(k_adjoint<1, false, false>);
-  }
+  const void* k = adjoint_kernel(fp, stored);
   // above 64 KiB the kernel must opt in before the occupancy query counts its blocks
   if (shm > 65536) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 64 * adj_waves(fp.precision), shm) != hipSuccess || nb < 1)
@@ -690,18 +729,7 @@ hipError_t launch_adjoint_tiles(const PlanView& pv, const FibreParams& fp, const
   hipLaunchKernelGGL(k_zero_counter2, dim3(1), dim3(1), 0, s, w.counter + 2);
   AdjArgs a{pv, fp, P, w, nmax, t_begin, t_end};
   const size_t shm = adjoint_lds_bytes(nmax, fp.grid_s, fp.n_steps, fp.precision);
-  const void* k;
-  if (fp.precision == 0) {
-    if (stored) k = fp.profile == 0 ? reinterpret_cast<const void*>(k_adjoint<0, true, true>)
-                                    : reinterpret_cast<const void*>(k_adjoint<0, false, true>);
-    else k = fp.profile == 0 ? reinterpret_cast<const void*>(k_adjoint<0, true, false>)
-                             : reinterpret_cast<const void*>(k_adjoint<0, false, false>);
-  } else {
-    if (stored) k = fp.profile == 0 ? reinterpret_cast<const void*>(k_adjoint<1, true, true>)
-                                    : reinterpret_cast<const void*>(k_adjoint<1, false, true>);
-    else k = fp.profile == 0 ? reinterpret_cast<const void*>(k_adjoint<1, true, false>)
-                             : reinterpret_cast<const void*>(k_adjoint<1, false, false>);
-  }
+  const void* k = adjoint_kernel(fp, stored);
   if (shm > 65536) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   void* args[] = {&a};
   hipError_t e = hipLaunchKernel(k, dim3(grid), dim3(64 * adj_waves(fp.precision)), args, shm, s);

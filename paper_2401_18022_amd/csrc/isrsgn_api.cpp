@@ -85,9 +85,9 @@ struct PlanEntry {
   uint64_t key = 0;
   std::vector<int> off;
   std::vector<double> f, R;
-  int n_batch = 0, n_total = 0, nmax = 0;
+  int n_batch = 0, n_total = 0, nmax = 0, nli = 1;
   int64_t n_tiles = 0;
-  DevBuf d_off, d_toff, d_f, d_R, d_alpha, d_aeff, d_gamma, d_cr;
+  DevBuf d_off, d_toff, d_f, d_R, d_alpha, d_aeff, d_gamma, d_cr, d_fpt, d_wpt;
   // workspace
   DevBuf abar, zm, dz, hdz32, ell64, lt32, ellL, tiles, pnli, snr, counter;
   DevBuf lr_a, lr_b, lr_rank, lr_res, lr_b64;  // low-rank form of lt32 (FP32 form, ODE profile)
@@ -108,6 +108,7 @@ struct PlanEntry {
     PlanView v;
     v.n_batch = n_batch;
     v.n_total = n_total;
+    v.nli = nli;
     v.n_tiles = n_tiles;
     v.off = d_off.as<int>();
     v.toff = d_toff.as<int64_t>();
@@ -117,6 +118,8 @@ struct PlanEntry {
     v.aeff = d_aeff.as<double>();
     v.gamma = d_gamma.as<double>();
     v.cr = d_cr.as<double>();
+    v.fpt = d_fpt.as<double>();
+    v.wpt = d_wpt.as<double>();
     return v;
   }
   Work work() const {
@@ -204,6 +207,8 @@ int validate_desc(const isrsgn_fibre_desc* d) {
   if (!(d->s_decades > 0) || d->s_decades > 40) return fail(ISRSGN_EINVAL, "s_decades must be in (0, 40]");
   if (d->ode_sub < 1 || d->ode_sub > 64) return fail(ISRSGN_EINVAL, "ode_sub must be in 1..64");
   if (d->n_spans < 1 || d->n_spans > 100000) return fail(ISRSGN_EINVAL, "n_spans must be in 1..100000");
+  if (!(d->rolloff >= 0.0 && d->rolloff <= 1.0)) return fail(ISRSGN_EINVAL, "rolloff must be in [0, 1]");
+  if (d->nli_points < 1 || d->nli_points > 64) return fail(ISRSGN_EINVAL, "nli_points must be in 1..64");
   if (!(d->cr_per_w_m_hz >= 0) || !(d->aeff_ref_m2 > 0)) return fail(ISRSGN_EINVAL, "need cr >= 0 and aeff_ref > 0");
   if (!(d->n2_m2_per_w >= 0) || !(d->gamma_const_per_w_m >= 0)) return fail(ISRSGN_EINVAL, "need n2, gamma >= 0");
   const double vals[] = {d->beta2, d->beta3, d->beta4, d->d_s_per_m2, d->s_s_per_m3, d->sdot_s_per_m4,
@@ -246,10 +251,11 @@ int validate_plan(const isrsgn_fibre* h, const isrsgn_plan* p, int64_t* ntiles_o
     for (int c = lo; c < hi; ++c) {
       if (!is_fin(p->f_hz[c]) || !(p->f_hz[c] > 0) || !is_fin(p->rs_hz[c]) || !(p->rs_hz[c] > 0))
         return fail(ISRSGN_EINVAL, "channel %d: need finite f > 0 and symbol rate > 0", c);
-      if (c > lo && p->f_hz[c] - p->f_hz[c - 1] < 0.5 * (p->rs_hz[c] + p->rs_hz[c - 1]))
-        return fail(ISRSGN_EINVAL, "plan %d: channels %d and %d are unsorted or overlap", b, c - 1 - lo, c - lo);
+      if (c > lo && p->f_hz[c] - p->f_hz[c - 1] < 0.5 * (1.0 + h->fp.rolloff) * (p->rs_hz[c] + p->rs_hz[c - 1]))
+        return fail(ISRSGN_EINVAL, "plan %d: channels %d and %d are unsorted or their spectra overlap", b, c - 1 - lo,
+                    c - lo);
     }
-    ntiles += (int64_t)n * n;
+    ntiles += (int64_t)n * n * h->fp.nli;
     if (n > nmax) nmax = n;
   }
   if (ntiles >= (int64_t)1 << 31) return fail(ISRSGN_EINVAL, "more than 2^31 tiles in one call");
@@ -291,16 +297,18 @@ int get_plan(isrsgn_fibre* h, const isrsgn_plan* p, hipStream_t s, PlanEntry** o
   e->n_total = total;
   e->n_tiles = ntiles;
   e->nmax = nmax;
+  e->nli = h->fp.nli;
   std::vector<int64_t> toff(p->n_batch + 1, 0);
   for (int b = 0; b < p->n_batch; ++b) {
     const int64_t n = p->ch_offsets[b + 1] - p->ch_offsets[b];
-    toff[b + 1] = toff[b] + n * n;
+    toff[b + 1] = toff[b] + n * n * e->nli;
   }
   const int M = h->desc.n_steps;
   const size_t nt = (size_t)total, nb = (size_t)p->n_batch;
   bool ok = e->d_off.ensure(sizeof(int) * (nb + 1)) && e->d_toff.ensure(sizeof(int64_t) * (nb + 1)) &&
             e->d_f.ensure(8 * nt) && e->d_R.ensure(8 * nt) && e->d_alpha.ensure(8 * nt) && e->d_aeff.ensure(8 * nt) &&
-            e->d_gamma.ensure(8 * nt) && e->d_cr.ensure(8 * nt) && e->abar.ensure(8 * nb) &&
+            e->d_gamma.ensure(8 * nt) && e->d_cr.ensure(8 * nt) && e->d_fpt.ensure(8 * nt * e->nli) &&
+            e->d_wpt.ensure(8 * nt * e->nli) && e->abar.ensure(8 * nb) &&
             e->zm.ensure(8 * nb * M) && e->dz.ensure(8 * nb * M) && e->hdz32.ensure(4 * nb * M) &&
             e->ell64.ensure(8 * nt * M) && e->ellL.ensure(8 * nt) && e->tiles.ensure(8 * (size_t)ntiles) &&
             e->pnli.ensure(8 * nt) && e->snr.ensure(8 * nt) && e->counter.ensure(64) &&
@@ -456,7 +464,7 @@ int prologue(isrsgn_fibre* h, PlanEntry* e, const double* P, const Work& w, bool
 int forward(isrsgn_fibre* h, PlanEntry* e, const double* P, const double* nf, double snr_trx, double* eta,
             double* pnli, double* tiles_out, double* snr, double* thr, bool keep_states, hipStream_t s, int* mk) {
   Work w = e->work();
-  if (tiles_out) w.tiles = tiles_out;
+  if (tiles_out && e->nli == 1) w.tiles = tiles_out;  // else folded over the COI points below
   const PlanView pv = e->view();
   int variant = 0, m1 = -1;
   const int rc = prologue(h, e, P, w, keep_states, s, &variant, &m1);
@@ -469,6 +477,8 @@ int forward(isrsgn_fibre* h, PlanEntry* e, const double* P, const double* nf, do
   add_span(h, 1, m1, m2);
   if ((err = launch_reduce(pv, h->fp, P, nf, snr_trx, w, eta, pnli, snr, thr, s)) != hipSuccess)
     return hip_fail(err, "reduction");
+  if (tiles_out && e->nli > 1 && (err = launch_fold_tiles(pv, w, tiles_out, s)) != hipSuccess)
+    return hip_fail(err, "tile output");
   *mk = mark(h, s);
   add_span(h, 2, m2, *mk);
   return ISRSGN_OK;
@@ -508,23 +518,23 @@ int ensure_grad_workspace(isrsgn_fibre* h, PlanEntry* e) {
                            (int64_t)(h->desc.precision == ISRSGN_FP32 ? sizeof(float2) : sizeof(double2));
   const int64_t max_tiles = store_mb > 0 ? (int64_t)(store_mb * 1048576.0 / (double)per_tile) : 0;
   bool fits = max_tiles > 0;
-  for (size_t b = 0; b < nb && fits; ++b) fits = e->off[b + 1] - e->off[b] <= max_tiles;
+  for (size_t b = 0; b < nb && fits; ++b) fits = (int64_t)(e->off[b + 1] - e->off[b]) * e->nli <= max_tiles;
   if (fits) {
     int64_t t = 0, t0 = 0, cnt = 0, most = 0;
     int g0 = 0;
     for (size_t b = 0; b < nb; ++b) {
-      const int n = e->off[b + 1] - e->off[b];
-      for (int i = 0; i < n; ++i) {
+      const int64_t row = (int64_t)(e->off[b + 1] - e->off[b]) * e->nli;  // tiles of one COI row
+      for (int i = 0; i < e->off[b + 1] - e->off[b]; ++i) {
         const int g = e->off[b] + i;  // global channel of this COI row
-        if (cnt + n > max_tiles && cnt > 0) {
+        if (cnt + row > max_tiles && cnt > 0) {
           e->batches.push_back({(unsigned int)t0, (unsigned int)t, g0, g});
           most = std::max(most, cnt);
           t0 = t;
           g0 = g;
           cnt = 0;
         }
-        t += n;
-        cnt += n;
+        t += row;
+        cnt += row;
       }
     }
     e->batches.push_back({(unsigned int)t0, (unsigned int)t, g0, e->n_total});
@@ -667,7 +677,9 @@ int run_graph(isrsgn_fibre* h, PlanEntry* e, int kind, const double* P, const do
     if (kind == kEta) {
       err = launch_copy(eta, o_a, (int64_t)nt, s);
       if (err == hipSuccess && pnli) err = launch_copy(pnli, o_b, (int64_t)nt, s);
-      if (err == hipSuccess && tiles) err = launch_copy(tiles, e->tiles.as<double>(), e->n_tiles, s);
+      if (err == hipSuccess && tiles)
+        err = e->nli == 1 ? launch_copy(tiles, e->tiles.as<double>(), e->n_tiles, s)
+                          : launch_fold_tiles(e->view(), e->work(), tiles, s);
     } else {
       err = launch_copy(snr, o_a, (int64_t)nt, s);
       if (err == hipSuccess) err = launch_copy(thr, o_t, (int64_t)nb, s);
@@ -746,6 +758,7 @@ size_t carve_noalloc(const isrsgn_fibre* h, int nb, int nt, int64_t ntiles, uint
   *pv = PlanView{};
   pv->n_batch = nb;
   pv->n_total = nt;
+  pv->nli = h->fp.nli;
   pv->n_tiles = ntiles;
   pv->off = reinterpret_cast<int*>(take(4 * (b + 1)));
   pv->toff = reinterpret_cast<int64_t*>(take(8 * (b + 1)));
@@ -755,6 +768,8 @@ size_t carve_noalloc(const isrsgn_fibre* h, int nb, int nt, int64_t ntiles, uint
   pv->aeff = reinterpret_cast<double*>(take(8 * n));
   pv->gamma = reinterpret_cast<double*>(take(8 * n));
   pv->cr = reinterpret_cast<double*>(take(8 * n));
+  pv->fpt = reinterpret_cast<double*>(take(8 * n * h->fp.nli));
+  pv->wpt = reinterpret_cast<double*>(take(8 * n * h->fp.nli));
   *w = Work{};
   w->abar = reinterpret_cast<double*>(take(8 * b));
   w->zm = reinterpret_cast<double*>(take(8 * b * M));
@@ -855,6 +870,8 @@ int isrsgn_setup_fibre(const isrsgn_fibre_desc* d, isrsgn_fibre** out) {
   fp.ode_sub = d->ode_sub;
   fp.precision = d->precision;
   fp.n_spans = d->n_spans;
+  fp.rolloff = d->rolloff;
+  fp.nli = d->nli_points;
   {
     const char* lr = std::getenv("ISRSGN_LOWRANK");
     const int cap = lr && *lr ? std::atoi(lr) : kRank;
@@ -956,7 +973,7 @@ int isrsgn_snr_noalloc(isrsgn_fibre* h, const isrsgn_plan* plan, const double* P
       const unsigned long long v = (unsigned long long)acc;
       if (q < nb) {
         const int64_t n = off[q + 1] - off[q];
-        acc += n * n;
+        acc += n * n * h->fp.nli;
       }
       return v;
     }, s);

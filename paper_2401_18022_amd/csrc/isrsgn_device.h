@@ -197,10 +197,10 @@ __device__ inline bool part_vrange(int part, double r, double slo, double shi, d
 
 // Channel data of the current plan in LDS.
 struct ChanLds {
-  double* lo_edge;  // f_c - R_c/2
-  double* hi_edge;  // f_c + R_c/2
+  double* lo_edge;  // f_c - (1 + beta) R_c/2: the lower edge of the spectrum's support
+  double* hi_edge;  // f_c + (1 + beta) R_c/2
   double* fc;
-  double* psd;      // G_c = P_c / R_c
+  double* psd;      // P_c / R_c: the flat part of the PSD
 };
 
 // Row layout of the current part in LDS: v_lo, dv (0: empty row), r, node weight.
@@ -208,14 +208,44 @@ struct RowLds {
   double *vlo, *dv, *r, *w;
 };
 
-__device__ inline void load_channels(const ChanLds& ch, const PlanView& pv, const double* P, int o, int n) {
+__device__ inline void load_channels(const ChanLds& ch, const PlanView& pv, const double* P, int o, int n,
+                                     double beta) {
   for (int c = threadIdx.x; c < n; c += blockDim.x) {
-    const double f = pv.f[o + c], R = pv.R[o + c];
+    const double f = pv.f[o + c], R = pv.R[o + c], hw = beta > 0.0 ? 0.5 * (1.0 + beta) * R : 0.5 * R;
     ch.fc[c] = f;
-    ch.lo_edge[c] = f - 0.5 * R;
-    ch.hi_edge[c] = f + 0.5 * R;
+    ch.lo_edge[c] = f - hw;
+    ch.hi_edge[c] = f + hw;
     ch.psd[c] = P[o + c] / R;
   }
+}
+
+// Raised-cosine spectrum relative to its flat part: 1 for |u| <= (1-beta) R/2, then
+// (1 + cos(pi (|u| - (1-beta) R/2) / (beta R))) / 2 to the support edge (u = F - f_c; beta > 0).
+__device__ inline double rc_shape(double u, double R, double beta) {
+  const double a = fabs(u), flat = 0.5 * (1.0 - beta) * R;
+  if (a <= flat) return 1.0;
+  return 0.5 * (1.0 + cospi((a - flat) / (beta * R)));
+}
+
+// The shape of channel c at F (its symbol rate from the support's half-width (1 + beta) R/2).
+__device__ inline double shape_at(const ChanLds& ch, int c, double F, double beta) {
+  return rc_shape(F - ch.fc[c], 2.0 * (ch.hi_edge[c] - ch.fc[c]) / (1.0 + beta), beta);
+}
+
+// Laplace transform M(a) = int g(u) exp(-a u) du of the unit-area raised cosine (rectangle: beta = 0):
+// sinhc(a R/2) cosh(a beta R/2) / (1 + (a beta R / pi)^2), and its derivative in a.
+__device__ inline double spectrum_m(double a, double R, double beta) {
+  const double s = sinhc(0.5 * a * R);
+  if (!(beta > 0.0)) return s;
+  const double h = 0.5 * beta * R, c = beta * R / kPi, ac = a * c;
+  return s * cosh(a * h) / (1.0 + ac * ac);
+}
+__device__ inline double spectrum_md(double a, double R, double beta) {
+  const double s = sinhc(0.5 * a * R), sd = 0.5 * R * sinhc_d(0.5 * a * R);
+  if (!(beta > 0.0)) return sd;
+  const double h = 0.5 * beta * R, c = beta * R / kPi, ac = a * c, d = 1.0 + ac * ac;
+  const double ch = cosh(a * h), shd = h * sinh(a * h);
+  return (sd * ch + s * shd) / d - s * ch * (2.0 * ac * c) / (d * d);
 }
 
 // Interpolation segment and weight of ln rho at F, given the channel c that holds F.
@@ -227,36 +257,49 @@ __device__ inline void segment(const ChanLds& ch, int n, int c, double F, int* s
   *t = (F - ch.fc[s]) / (ch.fc[s + 1] - ch.fc[s]);
 }
 
+// The f term of eq. (pk) at the NLI frequency F of COI i (fc: the plan's centres): the centre
+// itself (segment i, weight 0, exact for every i) or the interpolation segment holding F,
+// extrapolated with the end segments like f1 and f2.
+__device__ inline void nli_segment(const double* fc, int n, int i, double F, int* seg, double* t) {
+  if (F == fc[i] || n == 1) { *seg = i; *t = 0.0; return; }
+  int s = F >= fc[i] ? i : i - 1;
+  s = s < 0 ? 0 : (s > n - 2 ? n - 2 : s);
+  *seg = s;
+  *t = (F - fc[s]) / (fc[s + 1] - fc[s]);
+}
+
 // eq. (phi): phase mismatch per metre for offsets x, y and COI offset w from f_ref.
 __device__ inline double phase_mismatch(double x, double y, double w, double b2, double b3, double b4) {
   const double p4 = x * x + 1.5 * x * y + y * y + 3.0 * x * w + 3.0 * y * w + 3.0 * w * w;
   return -4.0 * kPi * kPi * x * y * (b2 + kPi * b3 * (x + y + 2.0 * w) + (2.0 * kPi * kPi / 3.0) * b4 * p4);
 }
 
-// Decode a global tile index into (plan, COI, interferer).
-__device__ inline void decode_tile(const PlanView& pv, unsigned int t, int* b, int* i, int* k) {
+// Decode a global tile index into (plan, COI, COI point, interferer): plan b's tiles are [i][j][k].
+__device__ inline void decode_tile(const PlanView& pv, unsigned int t, int* b, int* i, int* j, int* k) {
   int lo = 0, hi = pv.n_batch;
   while (hi - lo > 1) {
     int mid = (lo + hi) >> 1;
     if (pv.toff[mid] <= (int64_t)t) lo = mid; else hi = mid;
   }
   const int n = pv.off[lo + 1] - pv.off[lo];
-  const int64_t loc = (int64_t)t - pv.toff[lo];
+  const int64_t loc = (int64_t)t - pv.toff[lo], row = loc / n;
   *b = lo;
-  *i = (int)(loc / n);
+  *i = (int)(row / pv.nli);
+  *j = (int)(row % pv.nli);
   *k = (int)(loc % n);
 }
 
-// Geometry of tile (i,k) of the current plan.
+// Geometry of tile (i, j, k) of the current plan: fi is the NLI frequency of point j of COI i
+// (the centre f_i with one point).
 struct TileGeo {
   double fi, xp, xn, slo, shi, wi, gk;
   double lo0;  // lower edge of the plan's first channel
   float cinv;  // channels per Hz of the plan's lower edges, on average (0 for one channel)
 };
 
-__device__ inline TileGeo tile_geo(const ChanLds& ch, int n, int i, int k, double f_ref) {
+__device__ inline TileGeo tile_geo(const ChanLds& ch, int n, double fnli, int k, double f_ref) {
   TileGeo g;
-  g.fi = ch.fc[i];
+  g.fi = fnli;
   g.xp = ch.hi_edge[n - 1] - g.fi;
   g.xn = g.fi - ch.lo_edge[0];
   g.slo = ch.lo_edge[k] - g.fi;
@@ -374,6 +417,21 @@ __device__ inline bool make_node(const ChanLds& ch, const RowLds& rw, const Tile
   return true;
 }
 
+// Raised-cosine shapes of a node's f1, f2 and f3 relative to the flat PSDs (Node::gprod holds the
+// flat ones), recomputed from the node's row and column; called after the node's step sum, where
+// few registers are live (rolloff > 0 only).
+__device__ inline void node_shapes(const ChanLds& ch, const RowLds& rw, const TileGeo& g, int k, int part, int a,
+                                   int bcol, int c1, int c2, double beta, double* sh1, double* sh2, double* sh3) {
+  const double v = rw.vlo[a] + (bcol + 0.5) * rw.dv[a], r = rw.r[a];
+  const double ev = exp(v);
+  double x = r * ev, y = r / ev;
+  if (part == kQ3) { x = -x; y = -y; }
+  else if (part == kQ4) { y = -y; }
+  *sh1 = shape_at(ch, c1, g.fi + x, beta);
+  *sh2 = shape_at(ch, c2, g.fi + y, beta);
+  *sh3 = shape_at(ch, k, g.fi + x + y, beta);
+}
+
 // ---------------------------------------------------------------------------- step terms
 // Term m of S = sum_m p_m dz_m exp(j phi z_m) sinc(phi dz_m / 2) (eq. slow_vary), returned as
 // (re, im).  p_m = exp(E_m), E_m = [ln rho(f1) + ln rho(f2) + ln rho(f3) - ln rho(f_i)] / 2 (eq. pk);
@@ -430,8 +488,9 @@ __device__ inline void col_segments(int k, int n, int* sa, int* sb) {
   *sb = k > hi ? hi : k;
 }
 
+// sf, tf: the f term's segment and weight (nli_segment)
 template <bool kLinear>
-__device__ inline void load_cols(Col4* col, const float2* __restrict__ tab, int n, int M, int i, int k) {
+__device__ inline void load_cols(Col4* col, const float2* __restrict__ tab, int n, int M, int sf, double tf, int k) {
   int sa, sb;
   col_segments(k, n, &sa, &sb);
   for (int m = threadIdx.x; m < M; m += blockDim.x) {
@@ -441,7 +500,7 @@ __device__ inline void load_cols(Col4* col, const float2* __restrict__ tab, int 
     if (kLinear) {
       c.ax = 2.0f * A.x; c.ay = 2.0f * A.y; c.bx = 2.0f * B.x; c.by = 2.0f * B.y;
     } else {
-      const float li = row[i].x;
+      const float li = fmaf((float)tf, row[sf].y, row[sf].x);
       c.ax = A.x - li; c.ay = A.y; c.bx = B.x - li; c.by = B.y;
     }
     col[m] = c;
@@ -519,17 +578,16 @@ struct LowRank32 {
   const float4* __restrict__ a;  // LDS [M][kRank / 4]: a_r(m)
   float c[kRank];
   // b: the plan's [channel][kRank] (b_r, b_r(next channel) - b_r); f3 lies in segment s3 of the
-  // tile's column pair, f_i at the centre of channel i
-  __device__ void setup(const Term32& q, const float2* __restrict__ b, int s3, int i) {
+  // tile's column pair; bf: the tile's f term b_r at its NLI frequency (LDS, lowrank_f_term)
+  __device__ void setup(const Term32& q, const float2* __restrict__ b, int s3, const float* bf) {
     const float4* b1 = reinterpret_cast<const float4*>(b + (size_t)(q.o1 / sizeof(float2)) * kRank);
     const float4* b2 = reinterpret_cast<const float4*>(b + (size_t)(q.o2 / sizeof(float2)) * kRank);
     const float4* b3 = reinterpret_cast<const float4*>(b + (size_t)s3 * kRank);
-    const float4* bi = reinterpret_cast<const float4*>(b + (size_t)i * kRank);
 #pragma unroll
     for (int j = 0; j < kRank / 2; ++j) {
-      const float4 u = b1[j], v = b2[j], w = b3[j], x = bi[j];
-      c[2 * j] = (fmaf(q.t1, u.y, u.x) + fmaf(q.t2, v.y, v.x)) + (fmaf(q.t3, w.y, w.x) - x.x);
-      c[2 * j + 1] = (fmaf(q.t1, u.w, u.z) + fmaf(q.t2, v.w, v.z)) + (fmaf(q.t3, w.w, w.z) - x.z);
+      const float4 u = b1[j], v = b2[j], w = b3[j];
+      c[2 * j] = (fmaf(q.t1, u.y, u.x) + fmaf(q.t2, v.y, v.x)) + (fmaf(q.t3, w.y, w.x) - bf[2 * j]);
+      c[2 * j + 1] = (fmaf(q.t1, u.w, u.z) + fmaf(q.t2, v.w, v.z)) + (fmaf(q.t3, w.w, w.z) - bf[2 * j + 1]);
     }
   }
   // smallest terms first; the same order as the factorisation's FP32 check
@@ -546,6 +604,15 @@ struct LowRank32 {
     return e;
   }
 };
+
+// The f term of the low-rank exponent for one tile: bf_r = b_r(sf) + tf (b_r(sf + 1) - b_r(sf))
+// (b_r(sf) itself at a channel centre), written to LDS by the first kRank threads.
+__device__ inline void lowrank_f_term(const float2* __restrict__ b, int sf, float tf, float* bf) {
+  if (threadIdx.x < kRank) {
+    const float2 x = b[(size_t)sf * kRank + threadIdx.x];
+    bf[threadIdx.x] = tf == 0.0f ? x.x : fmaf(tf, x.y, x.x);
+  }
+}
 
 template <bool kLinear, class Src>
 __device__ inline float log2p32(const Term32& q, int m, float2 cab, const Src& src) {
@@ -706,10 +773,19 @@ __device__ inline void accumulate32(const Term32& q, const Split32& sp, const St
 // FP64 form of the same term (ocml sincospi / sinpi / exp on the FP64 table).
 struct Term64 {
   double phr, t1, t2, t3;
-  int s1, s2, s3, ci;
+  int s1, s2, s3;
 };
 
-__device__ inline Term64 term64_setup(const Node& nd, int i) {
+// The tile's f term of eq. (pk) per step (FP64 form): ln rho(z_m) at its NLI frequency, in LDS.
+__device__ inline void load_fcol64(double* lf, const double* __restrict__ tab, int n, int M, int sf, double tf) {
+  const int d = n > 1 ? 1 : 0;
+  for (int m = threadIdx.x; m < M; m += blockDim.x) {
+    const double* row = tab + (size_t)m * n;
+    lf[m] = tf == 0.0 ? row[sf] : row[sf] + tf * (row[sf + d] - row[sf]);
+  }
+}
+
+__device__ inline Term64 term64_setup(const Node& nd) {
   Term64 q;
   q.phr = nd.phr;
   q.t1 = nd.t1;
@@ -718,13 +794,14 @@ __device__ inline Term64 term64_setup(const Node& nd, int i) {
   q.s1 = nd.s1;
   q.s2 = nd.s2;
   q.s3 = nd.s3;
-  q.ci = i;
+
   return q;
 }
 
+// lf: the tile's f-term column (load_fcol64)
 template <bool kLinear>
 __device__ inline double2 term64(const Term64& q, int m, const double* __restrict__ zm, const double* __restrict__ dz,
-                                 const double* __restrict__ tab, int n) {
+                                 const double* __restrict__ tab, int n, const double* lf) {
   const double tt = q.phr * zm[m];
   double sn, cs;
   sincospi(2.0 * (tt - rint(tt)), &sn, &cs);
@@ -737,7 +814,7 @@ __device__ inline double2 term64(const Term64& q, int m, const double* __restric
     e = row[q.s3] + q.t3 * (row[q.s3 + d] - row[q.s3]);
   } else {
     e = 0.5 * ((row[q.s1] + q.t1 * (row[q.s1 + d] - row[q.s1])) + (row[q.s2] + q.t2 * (row[q.s2 + d] - row[q.s2])) +
-               (row[q.s3] + q.t3 * (row[q.s3 + d] - row[q.s3])) - row[q.ci]);
+               (row[q.s3] + q.t3 * (row[q.s3 + d] - row[q.s3])) - lf[m]);
   }
   const double amp = exp(e) * amp0;
   return make_double2(amp * cs, amp * sn);

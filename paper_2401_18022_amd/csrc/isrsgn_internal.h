@@ -17,7 +17,8 @@ constexpr int kRank = 8;            // terms of the low-rank FP32 profile table 
 struct PlanView {
   int n_batch;
   int n_total;           // channels over all plans
-  int64_t n_tiles;       // sum over plans of N_b^2
+  int nli;               // points of the within-channel NLI rule per COI
+  int64_t n_tiles;       // sum over plans of N_b^2 nli: tiles (i, j, k), j the COI's point
   const int* off;        // [n_batch + 1] channel offsets
   const int64_t* toff;   // [n_batch + 1] tile offsets
   const double* f;       // [n_total] centres
@@ -26,6 +27,8 @@ struct PlanView {
   double* aeff;          // [n_total] effective area at the centre
   double* gamma;         // [n_total] nonlinear coefficient
   double* cr;            // [n_total] Raman slope scaled by A_ref / A_eff
+  double* fpt;           // [n_total * nli] NLI frequency of point j of COI c
+  double* wpt;           // [n_total * nli] its weight q_j gamma(f_j)^2 / (gamma_c^2 R_c) in the tile row
 };
 
 struct FibreParams {
@@ -34,6 +37,8 @@ struct FibreParams {
   int profile, photon_ratio, n_steps, grid_s, grid_v, ode_sub, precision;
   int n_spans;  // identical spans: phased-array factor per node, n-fold ASE
   int lowrank;  // most terms of the low-rank profile table (kRank; ISRSGN_LOWRANK=N caps it, 0: table reads)
+  double rolloff;  // raised-cosine roll-off of every transmit spectrum (0: rectangular)
+  int nli;         // points of the within-channel NLI rule
   double s_decades;
   int n_tab;
   const double* tab_f;      // device copies of the tables
@@ -58,7 +63,7 @@ struct Work {
   double* lr_res;
   double* lr_b64;
   double* ellL;     // [n_total] ln rho(L, f_c)
-  double* tiles;    // [n_tiles]
+  double* tiles;    // [n_tiles]: plan b at toff[b], [i][j][k]
   double* pnli;     // [n_total]
   double* snr;      // [n_total]
   unsigned int* counter;  // work counter of the persistent tile kernels
@@ -112,6 +117,8 @@ size_t tile_lds(const FibreParams& fp, int nmax);
 int adjoint_blocks_per_cu(const FibreParams& fp, int nmax, bool stored);
 int tile_blocks_per_cu(const FibreParams& fp, int nmax, int variant);
 hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
+// The caller's N_b x N_b tile blocks from tiles (i, j, k): sum over the points j with their weights.
+hipError_t launch_fold_tiles(const PlanView& pv, const Work& w, double* out, hipStream_t s);
 // Up to kChunkWords 8-byte words carried to the device in the kernel's arguments (no copy from
 // host memory, so a captured launch keeps its values): dst[q] = words[q] for q < n.
 constexpr int kChunkWords = 240;

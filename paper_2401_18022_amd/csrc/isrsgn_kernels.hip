@@ -11,6 +11,10 @@ namespace {
 
 // ---------------------------------------------------------------------------- setup (Sec. II)
 
+__device__ inline double gamma_at(const FibreParams& fp, double f) {  // eq. (gamma)
+  return fp.gamma_const > 0 ? fp.gamma_const : 2.0 * kPi * fp.n2 * f / (kC * tab_at(fp.n_tab, fp.tab_f, fp.tab_aeff, f));
+}
+
 __global__ void k_channel_setup(PlanView pv, FibreParams fp) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= pv.n_total) return;
@@ -19,8 +23,23 @@ __global__ void k_channel_setup(PlanView pv, FibreParams fp) {
   double ae = tab_at(fp.n_tab, fp.tab_f, fp.tab_aeff, f);
   pv.alpha[c] = a;
   pv.aeff[c] = ae;
-  pv.gamma[c] = fp.gamma_const > 0 ? fp.gamma_const : 2.0 * kPi * fp.n2 * f / (kC * ae);  // eq. (gamma)
+  const double gc = fp.gamma_const > 0 ? fp.gamma_const : 2.0 * kPi * fp.n2 * f / (kC * ae);  // eq. (gamma)
+  pv.gamma[c] = gc;
   pv.cr[c] = fp.cr * fp.aeff_ref / ae;  // Raman gain scaled by A_eff at the channel frequency
+  // the within-channel NLI rule: nli midpoints of equal parts of the support (1 + beta) R, weights
+  // proportional to the receiver response (the spectrum's shape) and normalised to R, each point's
+  // tiles weighted by gamma(f_j)^2: w_j = q_j gamma(f_j)^2 / (gamma_c^2 R_c); one point: f_c, weight 1
+  const int J = fp.nli;
+  const double R = pv.R[c], d = (1.0 + fp.rolloff) * R / J;
+  double sum = 0.0;
+  for (int j = 0; j < J; ++j) sum += fp.rolloff > 0.0 ? rc_shape(f + (j + 0.5 - 0.5 * J) * d - f, R, fp.rolloff) : 1.0;
+  for (int j = 0; j < J; ++j) {
+    const double fj = f + (j + 0.5 - 0.5 * J) * d;
+    const double q = (fp.rolloff > 0.0 ? rc_shape(fj - f, R, fp.rolloff) : 1.0) / sum;
+    const double gr = gc > 0.0 ? gamma_at(fp, fj) / gc : 1.0;
+    pv.fpt[(size_t)c * J + j] = fj;
+    pv.wpt[(size_t)c * J + j] = q * gr * gr;
+  }
 }
 
 // ---------------------------------------------------------------------------- distance steps
@@ -55,8 +74,9 @@ __global__ void k_steps(PlanView pv, FibreParams fp, const double* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------- power profile
-// Closed form (linear Raman slope over a rectangular spectrum, uniform loss):
-//   ln rho(z,F) = -alpha z - a (F - f_ref) - ln sum_j (P_j/P_tot) exp(-a (f_j - f_ref)) sinhc(a R_j/2)
+// Closed form (linear Raman slope, uniform loss):
+//   ln rho(z,F) = -alpha z - a (F - f_ref) - ln sum_j (P_j/P_tot) exp(-a (f_j - f_ref)) M_j(a)
+// with M_j the transform of channel j's spectrum (sinhc(a R_j/2) for the rectangle)
 //   a = P_tot C_r L_eff(z).  Grid (M + 1, n_batch): row M is the span end.
 __global__ void k_profile_closed_form(PlanView pv, FibreParams fp, const double* __restrict__ P, Work w) {
   __shared__ double red[16];
@@ -72,7 +92,7 @@ __global__ void k_profile_closed_form(PlanView pv, FibreParams fp, const double*
     a = pt * cr * leff;
     double s = 0.0;
     for (int c = threadIdx.x; c < n; c += blockDim.x)
-      s += P[o + c] / pt * exp(-a * (pv.f[o + c] - fp.f_ref)) * sinhc(0.5 * a * pv.R[o + c]);
+      s += P[o + c] / pt * exp(-a * (pv.f[o + c] - fp.f_ref)) * spectrum_m(a, pv.R[o + c], fp.rolloff);
     s = block_sum(s, red);
     lnn = log(s);
   }
@@ -82,6 +102,7 @@ __global__ void k_profile_closed_form(PlanView pv, FibreParams fp, const double*
     else w.ellL[o + c] = l;
   }
 }
+
 
 // Raman power-evolution ODEs for ell_k = ln(P_k(z)/P_k(0)) (App. A):
 //   d ell_k/dz = -alpha_k + gain_k - loss_k
@@ -291,17 +312,27 @@ struct TileArgs {
 // lowrank: room for the plan's a_r(m) rows (FP32 form with the ODE profile only)
 __host__ __device__ inline size_t tile_lds_bytes(int nmax, int gs, int M, bool lowrank) {
   return sizeof(double) * (4 * (size_t)nmax + 4 * (size_t)gs + 4) +
-         (sizeof(StepLds) + sizeof(Col4) + (lowrank ? sizeof(float) * kRank : 0)) * (size_t)M + 16;
+         (sizeof(StepLds) + sizeof(Col4) + (lowrank ? sizeof(float) * kRank : 0)) * (size_t)M +
+         (lowrank ? sizeof(float) * kRank : 0) + 16;
 }
 
 __host__ __device__ inline bool tile_lowrank(const FibreParams& fp) { return fp.precision == 0 && fp.profile != 0; }
+
+__device__ inline double shape_product(const ChanLds& ch, const RowLds& rw, const TileGeo& g, int k, int part,
+                                       int64_t q, int GV, const Node& nd, double beta) {
+  double s1, s2, s3;
+  node_shapes(ch, rw, g, k, part, (int)(q / GV), (int)(q % GV), nd.c1, nd.c2, beta, &s1, &s2, &s3);
+  return s1 * s2 * s3;
+}
 
 // Forward pair-integral kernel.  Persistent: each workgroup takes tiles (b, i, k) from a
 // work counter; per tile it lays out the rows of each part in LDS, then strides the
 // part's grid_s x grid_v nodes across its 256 lanes (a wave covers consecutive nodes of a
 // row), accumulates node values w G1 G2 G3 |S|^2 in FP64 and reduces over the workgroup in
 // a fixed order, so results are bitwise reproducible.
-template <int kPrec, bool kLinear, int kUnroll, int kWaves>
+// kRc: raised-cosine spectra (the node's shapes multiply its value after the step sum; a separate
+// instantiation, so the rectangular kernels carry none of that code)
+template <int kPrec, bool kLinear, int kUnroll, int kWaves, bool kRc = false>
 __global__ void __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(kWaves > 0 ? kWaves : 1, 8)))
 k_tiles(TileArgs A) {
   extern __shared__ __align__(16) char smem_raw[];
@@ -316,7 +347,8 @@ k_tiles(TileArgs A) {
   StepLds* steps = reinterpret_cast<StepLds*>(d);
   Col4* col = reinterpret_cast<Col4*>(steps + M);
   float4* lra = reinterpret_cast<float4*>(col + M);  // the plan's a_r(m) of the low-rank table
-  unsigned int* tile_slot = reinterpret_cast<unsigned int*>(kPrec == 0 && !kLinear ? lra + M * (kRank / 4) : lra);
+  float* lr_bf = reinterpret_cast<float*>(kPrec == 0 && !kLinear ? lra + M * (kRank / 4) : lra);  // [kRank]
+  unsigned int* tile_slot = reinterpret_cast<unsigned int*>(lr_bf + (kPrec == 0 && !kLinear ? kRank : 0));
   const PlanView& pv = A.pv;
   int cur_b = -1, cur_lr = -1;
   for (;;) {
@@ -324,13 +356,19 @@ k_tiles(TileArgs A) {
     __syncthreads();
     const unsigned int t = *tile_slot;
     if (t >= A.t_end) break;
-    int b, i, k;
-    decode_tile(pv, t, &b, &i, &k);
+    int b, i, j, k;
+    decode_tile(pv, t, &b, &i, &j, &k);
     const int o = pv.off[b], n = pv.off[b + 1] - o;
     const double* zm = A.w.zm + (size_t)b * M;
     const double* dz = A.w.dz + (size_t)b * M;
+    const double fnli = pv.fpt[(size_t)(o + i) * pv.nli + j];  // the NLI frequency of this tile
+    int sf;
+    double tf;
+    nli_segment(pv.f + o, n, i, fnli, &sf, &tf);
+    sf = __builtin_amdgcn_readfirstlane(sf);  // tile-uniform: scalar registers
+    tf = uniform_f64(tf);
     if (b != cur_b) {
-      load_channels(ch, pv, A.P, o, n);
+      load_channels(ch, pv, A.P, o, n, A.fp.rolloff);
       if (kPrec == 0) load_steps(steps, zm, dz, A.w.hdz32 + (size_t)b * M, M);
       if (kPrec == 0 && !kLinear) {
         cur_lr = __builtin_amdgcn_readfirstlane(A.w.lr_rank[b]);
@@ -340,9 +378,13 @@ k_tiles(TileArgs A) {
       }
       cur_b = b;
     }
-    if (kPrec == 0) load_cols<kLinear>(col, A.w.lt32 + (size_t)M * o, n, M, i, k);
+    if (kPrec == 0) load_cols<kLinear>(col, A.w.lt32 + (size_t)M * o, n, M, sf, tf, k);
+    // FP64 form: the f-term column in the step-table slot (unused by that form)
+    double* lf64 = reinterpret_cast<double*>(steps);
+    if (kPrec == 1 && !kLinear) load_fcol64(lf64, A.w.ell64 + (size_t)M * o, n, M, sf, tf);
+    if (kPrec == 0 && !kLinear && cur_lr >= 0) lowrank_f_term(A.w.lr_b + (size_t)kRank * o, sf, (float)tf, lr_bf);
     __syncthreads();
-    const TileGeo g = uniform_geo(tile_geo(ch, n, i, k, A.fp.f_ref));
+    const TileGeo g = uniform_geo(tile_geo(ch, n, fnli, k, A.fp.f_ref));
     double acc = 0.0;
     unsigned int evaluated = 0;
     for (int part = kQ1; part <= kQ4; ++part) {
@@ -366,7 +408,7 @@ k_tiles(TileArgs A) {
             src.a = lra;
             int sa, sb;
             col_segments(k, n, &sa, &sb);
-            src.setup(tq, A.w.lr_b + (size_t)kRank * o, tq.up3 ? sb : sa, i);
+            src.setup(tq, A.w.lr_b + (size_t)kRank * o, tq.up3 ? sb : sa, lr_bf);
             accumulate32<kLinear, kUnroll>(tq, sp, steps, col, src, M, &sr, &si);
           } else {
             const Gather32 src{make_tab32(A.w.lt32 + (size_t)M * o, n, M), n};
@@ -375,20 +417,22 @@ k_tiles(TileArgs A) {
           s2v = (double)sr * sr + (double)si * si;
           if (A.w.s_store)
             static_cast<float2*>(A.w.s_store)[((int64_t)(t - A.t_begin) * 3 + part) * nodes + q] = make_float2(sr, si);
+          if constexpr (kRc) s2v *= shape_product(ch, rw, g, k, part, q, GV, nd, A.fp.rolloff);
         } else {
           if (!valid) continue;
-          const Term64 tq = term64_setup(nd, i);
+          const Term64 tq = term64_setup(nd);
           const double* tab = A.w.ell64 + (size_t)M * o;
           double sr = 0.0, si = 0.0;
 #pragma unroll kUnroll
           for (int m = 0; m < M; ++m) {
-            const double2 a = term64<kLinear>(tq, m, zm, dz, tab, n);
+            const double2 a = term64<kLinear>(tq, m, zm, dz, tab, n, lf64);
             sr += a.x;
             si += a.y;
           }
           s2v = sr * sr + si * si;
           if (A.w.s_store)
             static_cast<double2*>(A.w.s_store)[((int64_t)(t - A.t_begin) * 3 + part) * nodes + q] = make_double2(sr, si);
+          if constexpr (kRc) s2v *= shape_product(ch, rw, g, k, part, q, GV, nd, A.fp.rolloff);
         }
         acc += nd.w * nd.gprod * s2v;
         ++evaluated;
@@ -418,10 +462,18 @@ __global__ void k_reduce(PlanView pv, const double* __restrict__ P, const double
                          int n_spans) {
   const int g = g_begin + blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (g >= g_end) return;
-  const int b = plan_of_channel(pv, g), o = pv.off[b], n = pv.off[b + 1] - o, i = g - o;
-  const double* row = w.tiles + pv.toff[b] + (int64_t)i * n;
+  const int b = plan_of_channel(pv, g), o = pv.off[b], n = pv.off[b + 1] - o, i = g - o, J = pv.nli;
+  const double* row = w.tiles + pv.toff[b] + (int64_t)i * n * J;
   double s = 0.0;
-  for (int k = lane; k < n; k += 64) s += row[k];
+  if (J == 1) {
+    for (int k = lane; k < n; k += 64) s += row[k];
+  } else {  // the within-channel rule: tiles of point j weighted by w_j
+    for (int j = 0; j < J; ++j) {
+      double sj = 0.0;
+      for (int k = lane; k < n; k += 64) sj += row[(int64_t)j * n + k];
+      s += pv.wpt[(size_t)g * J + j] * sj;
+    }
+  }
   s = wave_sum(s);
   if (lane != 0) return;
   const double gm = pv.gamma[g], R = pv.R[g], f = pv.f[g], p = P[g];
@@ -493,6 +545,26 @@ __global__ void k_copy(double* __restrict__ dst, const double* __restrict__ src,
     dst[q] = src[q];
 }
 
+// The caller's tile blocks [i][k] = sum_j w_j tile(i, j, k) (plan b's output block at toff[b] / nli).
+__global__ void k_fold_tiles(PlanView pv, Work w, double* __restrict__ out) {
+  const int J = pv.nli;
+  const int64_t total = pv.n_tiles / J;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
+    int lo = 0, hi = pv.n_batch;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (pv.toff[mid] / J <= q) lo = mid; else hi = mid;
+    }
+    const int o = pv.off[lo], n = pv.off[lo + 1] - o;
+    const int64_t loc = q - pv.toff[lo] / J;
+    const int i = (int)(loc / n), k = (int)(loc % n);
+    const double* src = w.tiles + pv.toff[lo] + (int64_t)i * n * J + k;
+    double v = 0.0;
+    for (int j = 0; j < J; ++j) v += pv.wpt[(size_t)(o + i) * J + j] * src[(int64_t)j * n];
+    out[q] = v;
+  }
+}
+
 __global__ void k_put_words(unsigned long long* __restrict__ dst, WordChunk c) {
   const int q = threadIdx.x;
   if (q < c.n) dst[q] = c.w[q];
@@ -562,9 +634,13 @@ const TileKernel kTileKernels[2][2][kTileVariants] = {{ISRSGN_TILE_VARIANTS(0, f
                                                      {ISRSGN_TILE_VARIANTS(1, false), ISRSGN_TILE_VARIANTS(1, true)}};
 const char* const kTileVariantNames[kTileVariants] = {"unroll1", "unroll2", "unroll4", "unroll1-w4", "unroll2-w4",
                                                        "unroll4-w3"};
+// raised-cosine spectra: one kernel (unroll 2, no occupancy hint) for every variant index
+const TileKernel kTileKernelsRc[2][2] = {{k_tiles<0, false, 2, 0, true>, k_tiles<0, true, 2, 0, true>},
+                                         {k_tiles<1, false, 2, 0, true>, k_tiles<1, true, 2, 0, true>}};
 
 TileKernel tile_kernel(const FibreParams& fp, int variant) {
   const int v = variant < 0 || variant >= kTileVariants ? 0 : variant;
+  if (fp.rolloff > 0.0) return kTileKernelsRc[fp.precision ? 1 : 0][fp.profile == 0 ? 1 : 0];
   return kTileKernels[fp.precision ? 1 : 0][fp.profile == 0 ? 1 : 0][v];
 }
 
@@ -632,6 +708,12 @@ hipError_t launch_check_inputs(const double* P, const double* nf, int n, int* ou
 hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s) {
   const int64_t blocks = (n + 255) / 256 < 2048 ? (n + 255) / 256 : 2048;
   hipLaunchKernelGGL(k_copy, dim3((unsigned)(blocks < 1 ? 1 : blocks)), dim3(256), 0, s, dst, src, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_tiles(const PlanView& pv, const Work& w, double* out, hipStream_t s) {
+  const int64_t total = pv.n_tiles / pv.nli, blocks = (total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096;
+  hipLaunchKernelGGL(k_fold_tiles, dim3((unsigned)(blocks < 1 ? 1 : blocks)), dim3(256), 0, s, pv, w, out);
   return hipGetLastError();
 }
 

@@ -318,19 +318,20 @@ def single_channel(p_w: float = 1e-3, **fib) -> Workload:
     return Workload("single-ch", tiny_fibre(**fib), plan)
 
 
-def random_small(n_ch: int, seed: int, profile: int = PROFILE_ODE, **fib) -> Workload:
-    """A small C+L-like system with ragged spacing/symbol rates for parity tests."""
+def random_small(n_ch: int, seed: int, profile: int = PROFILE_ODE, rolloff: float = 0.0, **fib) -> Workload:
+    """A small C+L-like system with ragged spacing/symbol rates for parity tests (with a roll-off,
+    the spacing leaves room for the wider raised-cosine spectra)."""
     rng = np.random.default_rng(seed)
     rs = rng.uniform(30e9, 96e9, size=n_ch)
     gaps = rng.uniform(2e9, 40e9, size=n_ch)
     f = np.empty(n_ch)
     f[0] = 190e12
     for c in range(1, n_ch):
-        f[c] = f[c - 1] + 0.5 * (rs[c - 1] + rs[c]) + gaps[c]
+        f[c] = f[c - 1] + 0.5 * (1.0 + rolloff) * (rs[c - 1] + rs[c]) + gaps[c]
     p = dbm_to_w(rng.uniform(-2.0, 4.0, size=n_ch))
     plan = Plan(f, rs, p, nf_by_band(f), np.array([0, n_ch], dtype=np.int32))
     if profile == PROFILE_ODE:
         fb = cl_fibre(grid_s=16, grid_v=16, n_steps=24)
     else:
         fb = tiny_fibre(grid_s=16, grid_v=16, n_steps=24)
-    return Workload(f"rand-{n_ch}ch-s{seed}", fb.replace(**fib), plan)
+    return Workload(f"rand-{n_ch}ch-s{seed}", fb.replace(rolloff=rolloff, **fib), plan)
