@@ -60,8 +60,6 @@ def test_batch_golden_is_the_oracles():
 
 
 @pytest.mark.slow
-@pytest.mark.skipif(not os.path.exists(os.path.join(GOLDEN, "oracle_ou_grad_g32.json")),
-                    reason="oracle_ou_grad_g32.json not written yet (make_oracle_golden.py --only ou_grad_g32)")
 def test_grad_golden_is_the_oracles():
     """One COI row's SNR derivative along one direction, with the scalar dual type (independent of
     the 16-wide dual type that wrote the file)."""

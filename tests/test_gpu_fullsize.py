@@ -109,8 +109,6 @@ def test_ou_g128_fp32_and_fp64_forms_agree_on_every_channel():
     np.testing.assert_allclose(a["eta"], b["eta"], rtol=1e-4)
 
 
-@pytest.mark.skipif(not os.path.exists(os.path.join(GOLDEN, "oracle_ou_grad_g32.json")),
-                    reason="oracle_ou_grad_g32.json not written yet (make_oracle_golden.py --only ou_grad_g32)")
 @pytest.mark.parametrize("prec", [W.FP32, W.FP64])
 def test_ou_g32_gradient_matches_oracle_duals(prec):
     t = torch()
