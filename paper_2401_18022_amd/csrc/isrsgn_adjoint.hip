@@ -40,7 +40,7 @@ __global__ void k_fill(double* x, int64_t n) {
     x[q] = 0.0;
 }
 
-__global__ void k_zero_counter2(unsigned int* c) { *c = 0u; }
+__global__ void k_zero_counter2(unsigned int* c) { c[0] = c[1] = 0u; }
 
 // ---------------------------------------------------------------------------- adjoint pair integrals
 // For every node of tile (i,k) with upstream weight lam_i:
@@ -87,7 +87,7 @@ __host__ __device__ inline size_t adjoint_lds_bytes(int nmax, int gs, int M, int
   const int mc = prec == 0 ? 16 : 8;
   const size_t rb = prec == 0 ? 4 : 8;
   // (+1 double: the step tables start on a 16-byte boundary)
-  return sizeof(double) * (4 * (size_t)nmax + 4 * (size_t)gs + (size_t)nmax + 7 * (size_t)M + 8 + 1) +
+  return sizeof(double) * (4 * (size_t)nmax + 4 * (size_t)gs + (size_t)nmax + 7 * (size_t)M + 8 + 4 + 1) +
          (sizeof(StepLds) + sizeof(Col4)) * (size_t)M + adj_waves(prec) * (size_t)mc * stage_row(prec) * rb +
          adj_waves(prec) * 7 * kMetaStride * 4 + 16;
 }
@@ -164,8 +164,13 @@ struct AdjArgs {
 // kStored: S of every node comes from w.s_store, written by the forward tile kernel for the
 // same row batch, instead of a recomputing sweep over the steps.
 // kRc: raised-cosine spectra (node shapes in the G products; a separate instantiation)
-template <int kPrec, bool kLinear, bool kStored, bool kRc>
+// kLr: FP32 form with the ODE profile, where each plan has a low-rank table or not (lr_rank): the
+// kLr instantiation takes the tiles of plans that have one and evaluates the exponent from it,
+// the other takes the remaining tiles with table gathers.  (One kernel holding both step loops
+// needs more than 256 VGPRs and runs one wave per SIMD.)
+template <int kPrec, bool kLinear, bool kStored, bool kRc, bool kLr>
 __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
+  constexpr bool kSplit = kPrec == 0 && !kLinear;
   constexpr int kAdjWaves = adj_waves(kPrec), kAdjBlock = 64 * kAdjWaves;
   using real = typename AdjCfg<kPrec>::real;
   constexpr int MC = AdjCfg<kPrec>::MC;
@@ -184,6 +189,8 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
   d += 7 * M;
   double* red = d;
   d += 8;
+  float* lr_bf = reinterpret_cast<float*>(d);  // [kRank]: the tile's f term of the low-rank exponent
+  d += kRank / 2;
   d += (d - reinterpret_cast<double*>(smem_raw)) & 1;  // 16-byte boundary for the step tables
   StepLds* steps = reinterpret_cast<StepLds*>(d);
   Col4* col = reinterpret_cast<Col4*>(steps + M);
@@ -197,7 +204,15 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
                                           kAdjWaves * kMetaStride) + wv * kMetaStride;  // (f1, f2)
   unsigned int* tile_slot = reinterpret_cast<unsigned int*>(meta0 + 7 * kAdjWaves * kMetaStride);
   const PlanView& pv = A.pv;
-  unsigned int* counter = A.w.counter + 2;
+  unsigned int* counter = A.w.counter + (kLr ? 3 : 2);
+  if (kSplit && !kLr) {  // the gather form: nothing to do when every plan of the range has a table
+    int b0, b1, x0, x1, x2;
+    decode_tile(pv, A.t_begin, &b0, &x0, &x1, &x2);
+    decode_tile(pv, A.t_end - 1, &b1, &x0, &x1, &x2);
+    bool any = false;
+    for (int b = b0; b <= b1; ++b) any = any || A.w.lr_rank[b] < 0;
+    if (!any) return;
+  }
   int cur_b = -1;
   for (;;) {
     if (tid == 0) *tile_slot = A.t_begin + atomicAdd(counter, 1u);
@@ -215,7 +230,9 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
     nli_segment(pv.f + o, n, i, fnli, &sf, &tf);
     sf = __builtin_amdgcn_readfirstlane(sf);  // tile-uniform: scalar registers
     tf = uniform_f64(tf);
-    if (lam == 0.0) {  // COI outside the throughput (an empty channel): nothing flows back
+    // COI outside the throughput (an empty channel): nothing flows back; and the split form's
+    // tiles of the other instantiation
+    if (lam == 0.0 || (kSplit && (__builtin_amdgcn_readfirstlane(A.w.lr_rank[b]) >= 0) != kLr)) {
       __syncthreads();
       continue;
     }
@@ -225,6 +242,7 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
       cur_b = b;
     }
     if (kPrec == 0) load_cols<kLinear>(col, A.w.lt32 + (size_t)M * o, n, M, sf, tf, k);
+    if (kLr) lowrank_f_term(A.w.lr_b + (size_t)kRank * o, sf, (float)tf, lr_bf);
     // FP64 form: the f-term column in the step-table slot (unused by that form)
     double* lf64 = reinterpret_cast<double*>(steps);
     if (kPrec == 1 && !kLinear) load_fcol64(lf64, A.w.ell64 + (size_t)M * o, n, M, sf, tf);
@@ -304,9 +322,16 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
         if (valid && kPrec == 0) t32 = term32_setup(nd, k, n);
         Split32 sp{};
         if (kPrec == 0) sp = wave_split(valid, t32, steps, M);
-        // the f1 + f2 profile terms of the FP32 form: table gathers (the staging and re-map keep
-        // the LDS busy, so the low-rank form of the forward kernel does not pay here)
+        // the exponent of the FP32 form: the f1 + f2 profile terms by table gathers, or the whole
+        // exponent from the low-rank table (its step factors through scalar loads)
         const Gather32 gsrc{make_tab32(A.w.lt32 + (size_t)M * o, n, M), n};
+        LowRank32 lsrc;
+        if constexpr (kLr) {
+          lsrc.a = const_f32(A.w.lr_a + (size_t)M * kRank * b);
+          int sa, sb;
+          col_segments(k, n, &sa, &sb);
+          lsrc.setup(t32, A.w.lr_b + (size_t)kRank * o, t32.up3 ? sb : sa, lr_bf);
+        }
         if (valid) {
           if (kStored) {
             const int64_t slot = ((int64_t)(t - A.t_begin) * 3 + part) * nodes + q;
@@ -322,7 +347,8 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
             if (kPrec == 1) t64 = term64_setup(nd);
           } else if (kPrec == 0) {
             float a32, b32;
-            accumulate32<kLinear, 4>(t32, sp, steps, col, gsrc, M, &a32, &b32);
+            if constexpr (kLr) accumulate32<kLinear, 4>(t32, sp, steps, col, lsrc, M, &a32, &b32);
+            else accumulate32<kLinear, 4>(t32, sp, steps, col, gsrc, M, &a32, &b32);
             sr = a32;
             si = b32;
           } else {
@@ -352,7 +378,10 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
         for (int m0 = 0; m0 < M; m0 += MC) {
           if (kPrec == 0) {
             float* out = reinterpret_cast<float*>(my_stage) + lane;
-            stage_chunk32<kLinear, MC>(t32, valid, sp, m0, M, (float)cq, (float)sr, (float)si, steps, col, gsrc, out);
+            if constexpr (kLr)
+              stage_chunk32<kLinear, MC>(t32, valid, sp, m0, M, (float)cq, (float)sr, (float)si, steps, col, lsrc, out);
+            else
+              stage_chunk32<kLinear, MC>(t32, valid, sp, m0, M, (float)cq, (float)sr, (float)si, steps, col, gsrc, out);
           } else {
             for (int mm = 0; mm < MC; ++mm) {
               const int m = m0 + mm;
@@ -684,27 +713,38 @@ size_t adjoint_lds(int nmax, int gs, int M, int prec) { return adjoint_lds_bytes
 
 namespace {
 using AdjKernel = void (*)(AdjArgs);
+// (the low-rank instantiation exists for the FP32 form with the ODE profile only)
 #define ISRSGN_ADJ(P, RC)                                                                          \
-  {{k_adjoint<P, false, false, RC>, k_adjoint<P, false, true, RC>},                                \
-   {k_adjoint<P, true, false, RC>, k_adjoint<P, true, true, RC>}}
-// [precision][raised cosine][linear profile][stored S]
-const AdjKernel kAdjKernels[2][2][2][2] = {{ISRSGN_ADJ(0, false), ISRSGN_ADJ(0, true)},
-                                           {ISRSGN_ADJ(1, false), ISRSGN_ADJ(1, true)}};
+  {{{k_adjoint<P, false, false, RC, false>, k_adjoint<P, false, false, RC, P == 0>},               \
+    {k_adjoint<P, false, true, RC, false>, k_adjoint<P, false, true, RC, P == 0>}},                \
+   {{k_adjoint<P, true, false, RC, false>, k_adjoint<P, true, false, RC, false>},                  \
+    {k_adjoint<P, true, true, RC, false>, k_adjoint<P, true, true, RC, false>}}}
+// [precision][raised cosine][linear profile][stored S][low-rank]
+const AdjKernel kAdjKernels[2][2][2][2][2] = {{ISRSGN_ADJ(0, false), ISRSGN_ADJ(0, true)},
+                                              {ISRSGN_ADJ(1, false), ISRSGN_ADJ(1, true)}};
 
-const void* adjoint_kernel(const FibreParams& fp, bool stored) {
-  return reinterpret_cast<const void*>(
-      kAdjKernels[fp.precision ? 1 : 0][fp.rolloff > 0.0 ? 1 : 0][fp.profile == 0 ? 1 : 0][stored ? 1 : 0]);
+// FP32 form with the ODE profile: the tiles are split between the low-rank and gather forms
+bool adjoint_split(const FibreParams& fp) { return fp.precision == 0 && fp.profile != 0; }
+
+const void* adjoint_kernel(const FibreParams& fp, bool stored, bool lr) {
+  return reinterpret_cast<const void*>(kAdjKernels[fp.precision ? 1 : 0][fp.rolloff > 0.0 ? 1 : 0][fp.profile == 0 ? 1 : 0]
+                                                  [stored ? 1 : 0][lr && adjoint_split(fp) ? 1 : 0]);
 }
 }  // namespace
 
 int adjoint_blocks_per_cu(const FibreParams& fp, int nmax, bool stored) {
   int nb = 0;
   const size_t shm = adjoint_lds_bytes(nmax, fp.grid_s, fp.n_steps, fp.precision);
-  const void* k = adjoint_kernel(fp, stored);
-  // above 64 KiB the kernel must opt in before the occupancy query counts its blocks
-  if (shm > 65536) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 64 * adj_waves(fp.precision), shm) != hipSuccess || nb < 1)
-    nb = 1;
+  // the split form's two instantiations launch with the same grid: the fewer blocks of the two
+  for (int lr = 0; lr <= (adjoint_split(fp) ? 1 : 0); ++lr) {
+    const void* k = adjoint_kernel(fp, stored, lr != 0);
+    // above 64 KiB the kernel must opt in before the occupancy query counts its blocks
+    if (shm > 65536) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k, 64 * adj_waves(fp.precision), shm) != hipSuccess || b < 1)
+      b = 1;
+    nb = lr == 0 ? b : std::min(nb, b);
+  }
   return nb;
 }
 
@@ -729,11 +769,15 @@ hipError_t launch_adjoint_tiles(const PlanView& pv, const FibreParams& fp, const
   hipLaunchKernelGGL(k_zero_counter2, dim3(1), dim3(1), 0, s, w.counter + 2);
   AdjArgs a{pv, fp, P, w, nmax, t_begin, t_end};
   const size_t shm = adjoint_lds_bytes(nmax, fp.grid_s, fp.n_steps, fp.precision);
-  const void* k = adjoint_kernel(fp, stored);
-  if (shm > 65536) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  void* args[] = {&a};
-  hipError_t e = hipLaunchKernel(k, dim3(grid), dim3(64 * adj_waves(fp.precision)), args, shm, s);
-  if (e != hipSuccess) return e;
+  // split form: the low-rank instantiation (its own tile counter), then the gather one, which
+  // returns at once when every plan of the range has a low-rank table
+  for (int lr = adjoint_split(fp) ? 1 : 0; lr >= 0; --lr) {
+    const void* k = adjoint_kernel(fp, stored, lr != 0);
+    if (shm > 65536) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    void* args[] = {&a};
+    const hipError_t e = hipLaunchKernel(k, dim3(grid), dim3(64 * adj_waves(fp.precision)), args, shm, s);
+    if (e != hipSuccess) return e;
+  }
   return hipGetLastError();
 }
 

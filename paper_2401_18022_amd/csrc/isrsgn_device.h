@@ -573,9 +573,16 @@ struct Gather32 {
   }
 };
 
+// Global memory that no kernel writes while the reading kernel runs (the constant address space):
+// wave-uniform loads from it become scalar loads into SGPRs.
+using ConstF32 = const __attribute__((address_space(4))) float;
+__device__ inline ConstF32* const_f32(const float* p) { return (ConstF32*)p; }
+
 struct LowRank32 {
   static constexpr bool kAllTerms = true;
-  const float4* __restrict__ a;  // LDS [M][kRank / 4]: a_r(m)
+  // the plan's a_r(m), [M][kRank] in global memory: every lane of a wave reads the same step, so
+  // the reads are scalar loads and the factors sit in SGPRs (no LDS traffic, no VGPRs)
+  ConstF32* a;
   float c[kRank];
   // b: the plan's [channel][kRank] (b_r, b_r(next channel) - b_r); f3 lies in segment s3 of the
   // tile's column pair; bf: the tile's f term b_r at its NLI frequency (LDS, lowrank_f_term)
@@ -595,11 +602,11 @@ struct LowRank32 {
     float e = 0.0f;
 #pragma unroll
     for (int j = kRank / 4 - 1; j >= 0; --j) {
-      const float4 v = a[m * (kRank / 4) + j];
-      e = fmaf(v.w, c[4 * j + 3], e);
-      e = fmaf(v.z, c[4 * j + 2], e);
-      e = fmaf(v.y, c[4 * j + 1], e);
-      e = fmaf(v.x, c[4 * j], e);
+      ConstF32* v = a + m * kRank + 4 * j;
+      e = fmaf(v[3], c[4 * j + 3], e);
+      e = fmaf(v[2], c[4 * j + 2], e);
+      e = fmaf(v[1], c[4 * j + 1], e);
+      e = fmaf(v[0], c[4 * j], e);
     }
     return e;
   }

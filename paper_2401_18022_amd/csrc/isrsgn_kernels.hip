@@ -309,10 +309,9 @@ struct TileArgs {
   unsigned int t_end;
 };
 
-// lowrank: room for the plan's a_r(m) rows (FP32 form with the ODE profile only)
+// lowrank: room for the tile's f term of the low-rank exponent (FP32 form with the ODE profile only)
 __host__ __device__ inline size_t tile_lds_bytes(int nmax, int gs, int M, bool lowrank) {
-  return sizeof(double) * (4 * (size_t)nmax + 4 * (size_t)gs + 4) +
-         (sizeof(StepLds) + sizeof(Col4) + (lowrank ? sizeof(float) * kRank : 0)) * (size_t)M +
+  return sizeof(double) * (4 * (size_t)nmax + 4 * (size_t)gs + 4) + (sizeof(StepLds) + sizeof(Col4)) * (size_t)M +
          (lowrank ? sizeof(float) * kRank : 0) + 16;
 }
 
@@ -346,8 +345,7 @@ k_tiles(TileArgs A) {
   d += 4;
   StepLds* steps = reinterpret_cast<StepLds*>(d);
   Col4* col = reinterpret_cast<Col4*>(steps + M);
-  float4* lra = reinterpret_cast<float4*>(col + M);  // the plan's a_r(m) of the low-rank table
-  float* lr_bf = reinterpret_cast<float*>(kPrec == 0 && !kLinear ? lra + M * (kRank / 4) : lra);  // [kRank]
+  float* lr_bf = reinterpret_cast<float*>(col + M);  // [kRank]: the tile's f term of the low-rank exponent
   unsigned int* tile_slot = reinterpret_cast<unsigned int*>(lr_bf + (kPrec == 0 && !kLinear ? kRank : 0));
   const PlanView& pv = A.pv;
   int cur_b = -1, cur_lr = -1;
@@ -370,12 +368,7 @@ k_tiles(TileArgs A) {
     if (b != cur_b) {
       load_channels(ch, pv, A.P, o, n, A.fp.rolloff);
       if (kPrec == 0) load_steps(steps, zm, dz, A.w.hdz32 + (size_t)b * M, M);
-      if (kPrec == 0 && !kLinear) {
-        cur_lr = __builtin_amdgcn_readfirstlane(A.w.lr_rank[b]);
-        const float4* src = reinterpret_cast<const float4*>(A.w.lr_a + (size_t)M * kRank * b);
-        if (cur_lr >= 0)
-          for (int q = tid; q < M * (kRank / 4); q += kTileBlock) lra[q] = src[q];
-      }
+      if (kPrec == 0 && !kLinear) cur_lr = __builtin_amdgcn_readfirstlane(A.w.lr_rank[b]);
       cur_b = b;
     }
     if (kPrec == 0) load_cols<kLinear>(col, A.w.lt32 + (size_t)M * o, n, M, sf, tf, k);
@@ -405,7 +398,7 @@ k_tiles(TileArgs A) {
           float sr, si;
           if (!kLinear && cur_lr >= 0) {
             LowRank32 src;
-            src.a = lra;
+            src.a = const_f32(A.w.lr_a + (size_t)M * kRank * b);
             int sa, sb;
             col_segments(k, n, &sa, &sb);
             src.setup(tq, A.w.lr_b + (size_t)kRank * o, tq.up3 ? sb : sa, lr_bf);
