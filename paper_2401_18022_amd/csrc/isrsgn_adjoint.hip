@@ -110,23 +110,68 @@ __device__ inline void load_q4(const real* p, real* q) {
   }
 }
 
-// Pass 2 of the FP32 form for one chunk of MC steps: out[mm * row] = cq Re(conj(S) term_{m0+mm}),
-// each step in the form of the wave's range it falls in (zero past the last step).
+// Pass 2 of the FP32 form projects each step term on S: with S = |S| e^(2 pi j th),
+//   Re(conj(S) term_m) = |S| amp_m cos 2 pi (phr z_m - th)                  (midpoint forms)
+//                      = |S| p_m [s(z_(m+1/2)) - s(z_(m-1/2))] / (2 pi phr)  (edge form),
+// s(z) = sin 2 pi (phr z - th): one hardware sine or cosine per step instead of both.
+// NodePhase: cqs = cq |S| (the node's factor), th in FP32, hoff = 1/2 - th for the FP64 reduction.
+struct NodePhase {
+  float cqs, th;
+  double hoff;
+};
+
+// arg(x + j y) / (2 pi) in revolutions, FP32: octant reduction to t = min/max in [0, 1], then
+// atan(t) / (2 pi) as t P(t^2) with P of degree 7 (coefficients and their bound, 2.7e-8
+// revolutions, from fit_atan_rev.py).  x = y = 0 gives 0.
+__device__ inline float atan_rev32(float y, float x) {
+  const float ax = fabsf(x), ay = fabsf(y);
+  const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+  const float t = mx > 0.0f ? mn * __builtin_amdgcn_rcpf(mx) : 0.0f;
+  const float u = t * t;
+  float p = -0.000645301945f;
+  p = fmaf(p, u, 0.00347958924f);
+  p = fmaf(p, u, -0.00889871176f);
+  p = fmaf(p, u, 0.0153460251f);
+  p = fmaf(p, u, -0.0221362691f);
+  p = fmaf(p, u, 0.0317459442f);
+  p = fmaf(p, u, -0.0530461222f);
+  p = fmaf(p, u, 0.159154832f);
+  float r = p * t;
+  r = ay > ax ? 0.25f - r : r;
+  r = x < 0.0f ? 0.5f - r : r;
+  return y < 0.0f ? -r : r;
+}
+
+// s(z) at a step edge, the FP64 phase reduced to [-1/2, 1/2) revolutions.
+__device__ inline float edge_sine32(double phr, double z, double hoff) {
+  return __builtin_amdgcn_sinf((float)__builtin_amdgcn_fract(fma(phr, z, hoff)) - 0.5f);
+}
+
 template <bool kLinear, int kTier, class Src>
-__device__ inline void stage_range32(const Term32& t, int m0, int ma, int mb, float cq, float sr, float si,
+__device__ inline float term32_proj(const Term32& q, int m, const StepLds* __restrict__ st,
+                                    const Col4* __restrict__ col, const Src& src, const NodePhase& ph) {
+  const StepLds sv = st[m];
+  const float2 cab = col_pair(q, col, m);
+  // small form: |phr z_m| < 1/4 and |th| <= 1/2, within the hardware cosine's direct range
+  const float fr = kTier == kTierSmall ? fmaf(q.phrf, sv.zmf, -ph.th)
+                                       : (float)__builtin_amdgcn_fract(fma(q.phr, sv.zm, ph.hoff)) - 0.5f;
+  return amp32<kLinear, kTier>(q, m, sv, cab, src) * __builtin_amdgcn_cosf(fr);
+}
+
+// Pass 2 for one chunk of MC steps: out[mm * row] = cq Re(conj(S) term_{m0+mm}), each step in the
+// form of the wave's range it falls in (zero past the last step).
+template <bool kLinear, int kTier, class Src>
+__device__ inline void stage_range32(const Term32& t, int m0, int ma, int mb, const NodePhase& ph,
                                      const StepLds* __restrict__ st, const Col4* __restrict__ col, const Src& src,
                                      float* out) {
 #pragma unroll 2
-  for (int m = ma; m < mb; ++m) {
-    const float2 a = term32<kLinear, kTier>(t, m, st, col, src);
-    out[(m - m0) * kRow32] = cq * fmaf(sr, a.x, si * a.y);
-  }
+  for (int m = ma; m < mb; ++m) out[(m - m0) * kRow32] = ph.cqs * term32_proj<kLinear, kTier>(t, m, st, col, src, ph);
 }
 
 template <bool kLinear, int MC, class Src>
-__device__ inline void stage_chunk32(const Term32& t, bool valid, const Split32& sp, int m0, int M, float cq, float sr,
-                                     float si, const StepLds* __restrict__ st, const Col4* __restrict__ col,
-                                     const Src& src, float* out) {
+__device__ inline void stage_chunk32(const Term32& t, bool valid, const Split32& sp, int m0, int M, const NodePhase& ph,
+                                     const StepLds* __restrict__ st, const Col4* __restrict__ col, const Src& src,
+                                     float* out) {
   if (!valid) {  // one branch per chunk, not per step
 #pragma unroll
     for (int mm = 0; mm < MC; ++mm) out[mm * kRow32] = 0.0f;
@@ -134,18 +179,20 @@ __device__ inline void stage_chunk32(const Term32& t, bool valid, const Split32&
   }
   const int m1 = min(m0 + MC, M);
   if (sp.small) {
-    stage_range32<kLinear, kTierSmall>(t, m0, m0, m1, cq, sr, si, st, col, src, out);
+    stage_range32<kLinear, kTierSmall>(t, m0, m0, m1, ph, st, col, src, out);
   } else {
     const int pe = max(m0, min(sp.m_lo, m1)), xe = max(pe, min(sp.m_hi, m1));
-    if (pe > m0) stage_range32<kLinear, kTierPoly>(t, m0, m0, pe, cq, sr, si, st, col, src, out);
-    if (xe > pe) stage_range32<kLinear, kTierMixed>(t, m0, pe, xe, cq, sr, si, st, col, src, out);
-    if (m1 > xe) {  // edge form: terms carry 2 pi phr
-      const float c = cq * 0.5f * t.inv_piphr;
-      float2 e = lower_edge_phasor32(t.phr, st, xe);
+    if (pe > m0) stage_range32<kLinear, kTierPoly>(t, m0, m0, pe, ph, st, col, src, out);
+    if (xe > pe) stage_range32<kLinear, kTierMixed>(t, m0, pe, xe, ph, st, col, src, out);
+    if (m1 > xe) {  // edge form
+      const float c = ph.cqs * 0.5f * t.inv_piphr;
+      float s0 = edge_sine32(t.phr, xe > 0 ? st[xe - 1].zu : 0.0, ph.hoff);
 #pragma unroll 2
       for (int m = xe; m < m1; ++m) {
-        const float2 a = term32_edge<kLinear>(t, m, st, col, src, e);
-        out[(m - m0) * kRow32] = c * fmaf(sr, a.x, si * a.y);
+        const float s1 = edge_sine32(t.phr, st[m].zu, ph.hoff);
+        const float p = __builtin_amdgcn_exp2f(log2p32<kLinear>(t, m, col_pair(t, col, m), src));
+        out[(m - m0) * kRow32] = c * (p * (s1 - s0));
+        s0 = s1;
       }
     }
   }
@@ -374,14 +421,20 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
           }
         }
         real* my_stage = stage + (size_t)wv * MC * kRow;
+        NodePhase ph{0.0f, 0.0f, 0.5};
+        if (kPrec == 0 && valid) {
+          ph.cqs = (float)((double)cq * sqrt((double)sr * sr + (double)si * si));
+          ph.th = atan_rev32((float)si, (float)sr);
+          ph.hoff = 0.5 - (double)ph.th;
+        }
         // pass 2 in chunks of MC steps
         for (int m0 = 0; m0 < M; m0 += MC) {
           if (kPrec == 0) {
             float* out = reinterpret_cast<float*>(my_stage) + lane;
             if constexpr (kLr)
-              stage_chunk32<kLinear, MC>(t32, valid, sp, m0, M, (float)cq, (float)sr, (float)si, steps, col, lsrc, out);
+              stage_chunk32<kLinear, MC>(t32, valid, sp, m0, M, ph, steps, col, lsrc, out);
             else
-              stage_chunk32<kLinear, MC>(t32, valid, sp, m0, M, (float)cq, (float)sr, (float)si, steps, col, gsrc, out);
+              stage_chunk32<kLinear, MC>(t32, valid, sp, m0, M, ph, steps, col, gsrc, out);
           } else {
             for (int mm = 0; mm < MC; ++mm) {
               const int m = m0 + mm;

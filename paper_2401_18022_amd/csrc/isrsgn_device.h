@@ -634,6 +634,19 @@ __device__ inline float2 col_pair(const Term32& q, const Col4* __restrict__ col,
   return reinterpret_cast<const float2*>(col + m)[q.up3 ? 1 : 0];
 }
 
+// Amplitude of step m's term in the midpoint forms: p_m dz_m sinc(phi dz_m / 2).
+template <bool kLinear, int kTier, class Src>
+__device__ inline float amp32(const Term32& q, int m, const StepLds& sv, float2 cab, const Src& src) {
+  const float u2 = q.phrf2 * sv.c2;
+  float amp0 = sv.dz * fmaf(u2, fmaf(u2, fmaf(u2, -1.0f / 5040.0f, 1.0f / 120.0f), -1.0f / 6.0f), 1.0f);
+  if (kTier == kTierMixed) {  // both forms, then a per-lane select (no branch)
+    const float hh = q.phrf * sv.hdz;
+    const float as = __builtin_amdgcn_sinf(hh - rintf(hh)) * q.inv_piphr;
+    amp0 = u2 < 0.25f ? amp0 : as;
+  }
+  return __builtin_amdgcn_exp2f(log2p32<kLinear>(q, m, cab, src)) * amp0;
+}
+
 template <bool kLinear, int kTier, class Src>
 __device__ inline float2 term32(const Term32& q, int m, const StepLds* __restrict__ st, const Col4* __restrict__ col,
                                 const Src& src) {
@@ -648,15 +661,7 @@ __device__ inline float2 term32(const Term32& q, int m, const StepLds* __restric
   }
   const float sn = __builtin_amdgcn_sinf(fr);
   const float cs = __builtin_amdgcn_cosf(fr);
-  // amplitude dz_m sinc(phi dz_m / 2)
-  const float u2 = q.phrf2 * sv.c2;
-  float amp0 = sv.dz * fmaf(u2, fmaf(u2, fmaf(u2, -1.0f / 5040.0f, 1.0f / 120.0f), -1.0f / 6.0f), 1.0f);
-  if (kTier == kTierMixed) {  // both forms, then a per-lane select (no branch)
-    const float hh = q.phrf * sv.hdz;
-    const float as = __builtin_amdgcn_sinf(hh - rintf(hh)) * q.inv_piphr;
-    amp0 = u2 < 0.25f ? amp0 : as;
-  }
-  const float amp = __builtin_amdgcn_exp2f(log2p32<kLinear>(q, m, cab, src)) * amp0;
+  const float amp = amp32<kLinear, kTier>(q, m, sv, cab, src);
   return make_float2(amp * cs, amp * sn);
 }
 
