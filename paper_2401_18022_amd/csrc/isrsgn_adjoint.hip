@@ -64,9 +64,12 @@ __global__ void k_zero_counter2(unsigned int* c) { c[0] = c[1] = 0u; }
 //   (w3b = wgt - w3a - w3c); f1, f2: 1 when the node's f1 (f2) segment is the upper of its
 //   group's two.
 constexpr int kMetaStride = 72;  // >= 64 + 64 / MC for MC in {8, 16}
-// Workgroup of the adjoint: four wave64.  (The kernel holds over 168 VGPRs, so 2 waves per
-// SIMD; forcing 3 with six-wave groups spills registers and ran 1.7x slower.)
-__host__ __device__ constexpr int adj_waves(int) { return 4; }
+// Workgroup of the adjoint: kWaves wave64 sharing the tile's channel, row, step and accumulator
+// arrays in LDS; the staging and metadata are per wave.  Four waves hold up to 256 VGPRs (2 waves
+// per SIMD, register-bound); the FP32 form with the stored S also comes with sixteen waves,
+// held to 128 VGPRs (4 waves per SIMD; the node set-up spills) and one block per CU, used where
+// its LDS fits.
+constexpr int kAdjWavesMax = 16;
 // Row stride of the per-wave staging [step][node], in elements.  FP32: 68, so that a re-map
 // lane's run of node values starts on a 16-byte boundary (4 values per read); FP64: 65 (odd).
 // The node-lane writes of one step are consecutive either way.
@@ -83,13 +86,13 @@ struct AdjCfg<1> {
   static constexpr int MC = 8;
 };
 
-__host__ __device__ inline size_t adjoint_lds_bytes(int nmax, int gs, int M, int prec) {
+__host__ __device__ inline size_t adjoint_lds_bytes(int nmax, int gs, int M, int prec, int waves) {
   const int mc = prec == 0 ? 16 : 8;
   const size_t rb = prec == 0 ? 4 : 8;
   // (+1 double: the step tables start on a 16-byte boundary)
-  return sizeof(double) * (4 * (size_t)nmax + 4 * (size_t)gs + (size_t)nmax + 7 * (size_t)M + 8 + 4 + 1) +
-         (sizeof(StepLds) + sizeof(Col4)) * (size_t)M + adj_waves(prec) * (size_t)mc * stage_row(prec) * rb +
-         adj_waves(prec) * 7 * kMetaStride * 4 + 16;
+  return sizeof(double) * (4 * (size_t)nmax + 4 * (size_t)gs + (size_t)nmax + 7 * (size_t)M + kAdjWavesMax + 4 + 1) +
+         (sizeof(StepLds) + sizeof(Col4)) * (size_t)M + waves * (size_t)mc * stage_row(prec) * rb +
+         waves * 7 * kMetaStride * 4 + 16;
 }
 
 constexpr int kRow32 = stage_row(0);
@@ -215,10 +218,12 @@ struct AdjArgs {
 // kLr instantiation takes the tiles of plans that have one and evaluates the exponent from it,
 // the other takes the remaining tiles with table gathers.  (One kernel holding both step loops
 // needs more than 256 VGPRs and runs one wave per SIMD.)
-template <int kPrec, bool kLinear, bool kStored, bool kRc, bool kLr>
-__global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
+// kWaves: waves per workgroup (4, or 16 with at least 4 waves per SIMD).
+template <int kPrec, bool kLinear, bool kStored, bool kRc, bool kLr, int kWaves>
+__global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(kWaves / 4)))
+k_adjoint(AdjArgs A) {
   constexpr bool kSplit = kPrec == 0 && !kLinear;
-  constexpr int kAdjWaves = adj_waves(kPrec), kAdjBlock = 64 * kAdjWaves;
+  constexpr int kAdjWaves = kWaves, kAdjBlock = 64 * kAdjWaves;
   using real = typename AdjCfg<kPrec>::real;
   constexpr int MC = AdjCfg<kPrec>::MC;
   constexpr int NG = 64 / MC;  // node groups per wave in the re-mapped phase
@@ -234,8 +239,8 @@ __global__ void __launch_bounds__(64 * adj_waves(kPrec)) k_adjoint(AdjArgs A) {
   d += nmax;
   double* tacc = d;  // [7][M]: the tile's hot channels k-1, k, k+1, i-1, i, i+1; row 6: the f term
   d += 7 * M;
-  double* red = d;
-  d += 8;
+  double* red = d;  // [kAdjWavesMax]: block_sum
+  d += kAdjWavesMax;
   float* lr_bf = reinterpret_cast<float*>(d);  // [kRank]: the tile's f term of the low-rank exponent
   d += kRank / 2;
   d += (d - reinterpret_cast<double*>(smem_raw)) & 1;  // 16-byte boundary for the step tables
@@ -762,40 +767,49 @@ __global__ void k_grad_final(PlanView pv, Work w, double* dthr) {
 
 }  // namespace
 
-size_t adjoint_lds(int nmax, int gs, int M, int prec) { return adjoint_lds_bytes(nmax, gs, M, prec); }
+size_t adjoint_lds(int nmax, int gs, int M, int prec) { return adjoint_lds_bytes(nmax, gs, M, prec, 4); }
 
 namespace {
 using AdjKernel = void (*)(AdjArgs);
 // (the low-rank instantiation exists for the FP32 form with the ODE profile only)
+// [low-rank][wide]: the sixteen-wave form exists for the FP32 form with the stored S only (the
+// narrow kernel stands in elsewhere); the low-rank one for the FP32 form with the ODE profile
+#define ISRSGN_ADJ_LW(P, L, S, RC)                                                                 \
+  {{k_adjoint<P, L, S, RC, false, 4>, k_adjoint<P, L, S, RC, false, (P == 0 && S) ? 16 : 4>},       \
+   {k_adjoint<P, L, S, RC, P == 0 && !L, 4>, k_adjoint<P, L, S, RC, P == 0 && !L, (P == 0 && S) ? 16 : 4>}}
 #define ISRSGN_ADJ(P, RC)                                                                          \
-  {{{k_adjoint<P, false, false, RC, false>, k_adjoint<P, false, false, RC, P == 0>},               \
-    {k_adjoint<P, false, true, RC, false>, k_adjoint<P, false, true, RC, P == 0>}},                \
-   {{k_adjoint<P, true, false, RC, false>, k_adjoint<P, true, false, RC, false>},                  \
-    {k_adjoint<P, true, true, RC, false>, k_adjoint<P, true, true, RC, false>}}}
-// [precision][raised cosine][linear profile][stored S][low-rank]
-const AdjKernel kAdjKernels[2][2][2][2][2] = {{ISRSGN_ADJ(0, false), ISRSGN_ADJ(0, true)},
-                                              {ISRSGN_ADJ(1, false), ISRSGN_ADJ(1, true)}};
+  {{ISRSGN_ADJ_LW(P, false, false, RC), ISRSGN_ADJ_LW(P, false, true, RC)},                        \
+   {ISRSGN_ADJ_LW(P, true, false, RC), ISRSGN_ADJ_LW(P, true, true, RC)}}
+// [precision][raised cosine][linear profile][stored S][low-rank][wide]
+const AdjKernel kAdjKernels[2][2][2][2][2][2] = {{ISRSGN_ADJ(0, false), ISRSGN_ADJ(0, true)},
+                                                 {ISRSGN_ADJ(1, false), ISRSGN_ADJ(1, true)}};
 
 // FP32 form with the ODE profile: the tiles are split between the low-rank and gather forms
 bool adjoint_split(const FibreParams& fp) { return fp.precision == 0 && fp.profile != 0; }
 
-const void* adjoint_kernel(const FibreParams& fp, bool stored, bool lr) {
+// Waves per workgroup: sixteen for the FP32 form with the stored S when that layout's LDS fits
+int adjoint_waves(const FibreParams& fp, int nmax, bool stored, size_t lds_max) {
+  const bool wide = fp.precision == 0 && stored && adjoint_lds_bytes(nmax, fp.grid_s, fp.n_steps, 0, 16) <= lds_max;
+  return wide ? 16 : 4;
+}
+
+const void* adjoint_kernel(const FibreParams& fp, bool stored, bool lr, int waves) {
   return reinterpret_cast<const void*>(kAdjKernels[fp.precision ? 1 : 0][fp.rolloff > 0.0 ? 1 : 0][fp.profile == 0 ? 1 : 0]
-                                                  [stored ? 1 : 0][lr && adjoint_split(fp) ? 1 : 0]);
+                                                  [stored ? 1 : 0][lr && adjoint_split(fp) ? 1 : 0][waves == 16 ? 1 : 0]);
 }
 }  // namespace
 
-int adjoint_blocks_per_cu(const FibreParams& fp, int nmax, bool stored) {
+int adjoint_blocks_per_cu(const FibreParams& fp, int nmax, bool stored, size_t lds_max) {
   int nb = 0;
-  const size_t shm = adjoint_lds_bytes(nmax, fp.grid_s, fp.n_steps, fp.precision);
+  const int waves = adjoint_waves(fp, nmax, stored, lds_max);
+  const size_t shm = adjoint_lds_bytes(nmax, fp.grid_s, fp.n_steps, fp.precision, waves);
   // the split form's two instantiations launch with the same grid: the fewer blocks of the two
   for (int lr = 0; lr <= (adjoint_split(fp) ? 1 : 0); ++lr) {
-    const void* k = adjoint_kernel(fp, stored, lr != 0);
+    const void* k = adjoint_kernel(fp, stored, lr != 0, waves);
     // above 64 KiB the kernel must opt in before the occupancy query counts its blocks
     if (shm > 65536) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     int b = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k, 64 * adj_waves(fp.precision), shm) != hipSuccess || b < 1)
-      b = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k, 64 * waves, shm) != hipSuccess || b < 1) b = 1;
     nb = lr == 0 ? b : std::min(nb, b);
   }
   return nb;
@@ -818,17 +832,19 @@ hipError_t launch_grad_rows(const PlanView& pv, const FibreParams& fp, const dou
 }
 
 hipError_t launch_adjoint_tiles(const PlanView& pv, const FibreParams& fp, const double* P, const Work& w, int nmax,
-                                int grid, unsigned int t_begin, unsigned int t_end, bool stored, hipStream_t s) {
+                                int grid, unsigned int t_begin, unsigned int t_end, bool stored, size_t lds_max,
+                                hipStream_t s) {
   hipLaunchKernelGGL(k_zero_counter2, dim3(1), dim3(1), 0, s, w.counter + 2);
   AdjArgs a{pv, fp, P, w, nmax, t_begin, t_end};
-  const size_t shm = adjoint_lds_bytes(nmax, fp.grid_s, fp.n_steps, fp.precision);
+  const int waves = adjoint_waves(fp, nmax, stored, lds_max);
+  const size_t shm = adjoint_lds_bytes(nmax, fp.grid_s, fp.n_steps, fp.precision, waves);
   // split form: the low-rank instantiation (its own tile counter), then the gather one, which
   // returns at once when every plan of the range has a low-rank table
   for (int lr = adjoint_split(fp) ? 1 : 0; lr >= 0; --lr) {
-    const void* k = adjoint_kernel(fp, stored, lr != 0);
+    const void* k = adjoint_kernel(fp, stored, lr != 0, waves);
     if (shm > 65536) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     void* args[] = {&a};
-    const hipError_t e = hipLaunchKernel(k, dim3(grid), dim3(64 * adj_waves(fp.precision)), args, shm, s);
+    const hipError_t e = hipLaunchKernel(k, dim3(grid), dim3(64 * waves), args, shm, s);
     if (e != hipSuccess) return e;
   }
   return hipGetLastError();

@@ -558,7 +558,7 @@ int enqueue_grad_stored(isrsgn_fibre* h, PlanEntry* e, const double* P, const do
   w.s_store = e->s_store.p;
   hipError_t err = launch_grad_init(pv, h->fp, w, s);
   if (err != hipSuccess) return hip_fail(err, "adjoint");
-  const int adj_per_cu = adjoint_blocks_per_cu(h->fp, e->nmax, true);
+  const int adj_per_cu = adjoint_blocks_per_cu(h->fp, e->nmax, true, h->lds_max);
   bool first = true;
   for (const auto& bt : e->batches) {
     const int64_t nt = (int64_t)bt.t1 - bt.t0;
@@ -575,8 +575,8 @@ int enqueue_grad_stored(isrsgn_fibre* h, PlanEntry* e, const double* P, const do
     const int mb = mark(h, s);
     add_span(h, 2, ma, mb);
     const int64_t grid = std::min<int64_t>((int64_t)adj_per_cu * h->n_cu, nt);
-    if ((err = launch_adjoint_tiles(pv, h->fp, P, w, e->nmax, (int)(grid < 1 ? 1 : grid), bt.t0, bt.t1, true, s)) !=
-        hipSuccess)
+    if ((err = launch_adjoint_tiles(pv, h->fp, P, w, e->nmax, (int)(grid < 1 ? 1 : grid), bt.t0, bt.t1, true,
+                                    h->lds_max, s)) != hipSuccess)
       return hip_fail(err, "adjoint");
     mk = mark(h, s);
     add_span(h, 3, mb, mk);
@@ -598,7 +598,7 @@ int enqueue_call(isrsgn_fibre* h, PlanEntry* e, int kind, const double* P, const
   int rc = forward(h, e, P, nf, snr_trx, eta, pnli, tiles, snr, thr,
                    kind == kGrad && h->desc.profile == ISRSGN_PROFILE_ODE, s, &m3);
   if (rc || kind != kGrad) return rc;
-  const int per_cu = adjoint_blocks_per_cu(h->fp, e->nmax, false);
+  const int per_cu = adjoint_blocks_per_cu(h->fp, e->nmax, false, h->lds_max);
   int64_t grid = (int64_t)per_cu * h->n_cu;
   if (grid > e->n_tiles) grid = e->n_tiles;
   const Work w = e->work();
@@ -607,7 +607,7 @@ int enqueue_call(isrsgn_fibre* h, PlanEntry* e, int kind, const double* P, const
   if (err == hipSuccess) err = launch_grad_rows(pv, h->fp, P, nf, snr_trx, w, 0, pv.n_total, s);
   if (err == hipSuccess)
     err = launch_adjoint_tiles(pv, h->fp, P, w, e->nmax, (int)(grid < 1 ? 1 : grid), 0u, (unsigned int)e->n_tiles,
-                               false, s);
+                               false, h->lds_max, s);
   if (err != hipSuccess) return hip_fail(err, "adjoint");
   const int m4 = mark(h, s);
   add_span(h, 3, m3, m4);
@@ -825,7 +825,7 @@ int noalloc_variant(isrsgn_fibre* h) {
   read_tune_file();
   for (auto& kv : g_tuned)
     if (kv.first == key) return kv.second;
-  return h->desc.precision == ISRSGN_FP32 ? 4 : 0;  // unroll 2 at 4 waves/SIMD; FP64: unroll 1
+  return h->desc.precision == ISRSGN_FP32 ? 2 : 0;  // unroll 2 at 5 waves/SIMD; FP64: unroll 1
 }
 
 }  // namespace

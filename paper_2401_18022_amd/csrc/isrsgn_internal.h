@@ -108,13 +108,15 @@ hipError_t launch_copy_profile(const PlanView& pv, const FibreParams& fp, const 
 hipError_t launch_grad_init(const PlanView& pv, const FibreParams& fp, const Work& w, hipStream_t s);
 hipError_t launch_grad_rows(const PlanView& pv, const FibreParams& fp, const double* P, const double* nf,
                             double snr_trx, const Work& w, int g_begin, int g_end, hipStream_t s);
+// lds_max: LDS one workgroup may allocate (picks the sixteen-wave form where it fits)
 hipError_t launch_adjoint_tiles(const PlanView& pv, const FibreParams& fp, const double* P, const Work& w, int nmax,
-                                int grid, unsigned int t_begin, unsigned int t_end, bool stored, hipStream_t s);
+                                int grid, unsigned int t_begin, unsigned int t_end, bool stored, size_t lds_max,
+                                hipStream_t s);
 hipError_t launch_grad_finish(const PlanView& pv, const FibreParams& fp, const double* P, const Work& w,
                               double* coef, double* dthr, hipStream_t s);
-size_t adjoint_lds(int nmax, int gs, int M, int prec);
+size_t adjoint_lds(int nmax, int gs, int M, int prec);  // the four-wave form's (the smallest)
 size_t tile_lds(const FibreParams& fp, int nmax);
-int adjoint_blocks_per_cu(const FibreParams& fp, int nmax, bool stored);
+int adjoint_blocks_per_cu(const FibreParams& fp, int nmax, bool stored, size_t lds_max);
 int tile_blocks_per_cu(const FibreParams& fp, int nmax, int variant);
 hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
 // The caller's N_b x N_b tile blocks from tiles (i, j, k): sum over the points j with their weights.

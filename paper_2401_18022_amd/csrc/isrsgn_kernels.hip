@@ -621,11 +621,11 @@ namespace {
 // Tile-kernel variants (step-loop unroll, minimum waves per SIMD), chosen by the host autotuner.
 using TileKernel = void (*)(TileArgs);
 #define ISRSGN_TILE_VARIANTS(P, L)                                                                 \
-  {k_tiles<P, L, 1, 0>, k_tiles<P, L, 2, 0>, k_tiles<P, L, 4, 0>, k_tiles<P, L, 1, 4>, k_tiles<P, L, 2, 4>, \
+  {k_tiles<P, L, 1, 0>, k_tiles<P, L, 2, 0>, k_tiles<P, L, 2, 5>, k_tiles<P, L, 1, 4>, k_tiles<P, L, 2, 4>, \
    k_tiles<P, L, 4, 3>}
 const TileKernel kTileKernels[2][2][kTileVariants] = {{ISRSGN_TILE_VARIANTS(0, false), ISRSGN_TILE_VARIANTS(0, true)},
                                                      {ISRSGN_TILE_VARIANTS(1, false), ISRSGN_TILE_VARIANTS(1, true)}};
-const char* const kTileVariantNames[kTileVariants] = {"unroll1", "unroll2", "unroll4", "unroll1-w4", "unroll2-w4",
+const char* const kTileVariantNames[kTileVariants] = {"unroll1", "unroll2", "unroll2-w5", "unroll1-w4", "unroll2-w4",
                                                        "unroll4-w3"};
 // raised-cosine spectra: one kernel (unroll 2, no occupancy hint) for every variant index
 const TileKernel kTileKernelsRc[2][2] = {{k_tiles<0, false, 2, 0, true>, k_tiles<0, true, 2, 0, true>},
