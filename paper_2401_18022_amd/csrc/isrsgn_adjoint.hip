@@ -90,7 +90,7 @@ __host__ __device__ inline size_t adjoint_lds_bytes(int nmax, int gs, int M, int
   const int mc = prec == 0 ? 16 : 8;
   const size_t rb = prec == 0 ? 4 : 8;
   // (+1 double: the step tables start on a 16-byte boundary)
-  return sizeof(double) * (4 * (size_t)nmax + 4 * (size_t)gs + (size_t)nmax + 7 * (size_t)M + kAdjWavesMax + 4 + 1) +
+  return sizeof(double) * (3 * (size_t)nmax + 4 * (size_t)gs + (size_t)nmax + 7 * (size_t)M + kAdjWavesMax + 4 + 1) +
          (sizeof(StepLds) + sizeof(Col4)) * (size_t)M + waves * (size_t)mc * stage_row(prec) * rb +
          waves * 7 * kMetaStride * 4 + 16;
 }
@@ -231,8 +231,8 @@ k_adjoint(AdjArgs A) {
   const int nmax = A.nmax, GS = A.fp.grid_s, GV = A.fp.grid_v, M = A.fp.n_steps, tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   double* d = reinterpret_cast<double*>(smem_raw);
-  const ChanLds ch{d, d + nmax, d + 2 * nmax, d + 3 * nmax};
-  d += 4 * nmax;
+  const ChanLds ch{d, d + nmax, d + 2 * nmax};
+  d += 3 * nmax;
   const RowLds rw{d, d + GS, d + 2 * GS, d + 3 * GS};
   d += 4 * GS;
   double* gGl = d;

@@ -197,10 +197,12 @@ __device__ inline bool part_vrange(int part, double r, double slo, double shi, d
 
 // Channel data of the current plan in LDS.
 struct ChanLds {
-  double* lo_edge;  // f_c - (1 + beta) R_c/2: the lower edge of the spectrum's support
-  double* hi_edge;  // f_c + (1 + beta) R_c/2
   double* fc;
-  double* psd;      // P_c / R_c: the flat part of the PSD
+  double* hw;   // (1 + beta) R_c/2: half the width of the spectrum's support
+  double* psd;  // P_c / R_c: the flat part of the PSD
+  // the support's edges (the same FP64 operations wherever they are formed)
+  __device__ double lo(int c) const { return fc[c] - hw[c]; }
+  __device__ double hi(int c) const { return fc[c] + hw[c]; }
 };
 
 // Row layout of the current part in LDS: v_lo, dv (0: empty row), r, node weight.
@@ -213,8 +215,7 @@ __device__ inline void load_channels(const ChanLds& ch, const PlanView& pv, cons
   for (int c = threadIdx.x; c < n; c += blockDim.x) {
     const double f = pv.f[o + c], R = pv.R[o + c], hw = beta > 0.0 ? 0.5 * (1.0 + beta) * R : 0.5 * R;
     ch.fc[c] = f;
-    ch.lo_edge[c] = f - hw;
-    ch.hi_edge[c] = f + hw;
+    ch.hw[c] = hw;
     ch.psd[c] = P[o + c] / R;
   }
 }
@@ -229,7 +230,7 @@ __device__ inline double rc_shape(double u, double R, double beta) {
 
 // The shape of channel c at F (its symbol rate from the support's half-width (1 + beta) R/2).
 __device__ inline double shape_at(const ChanLds& ch, int c, double F, double beta) {
-  return rc_shape(F - ch.fc[c], 2.0 * (ch.hi_edge[c] - ch.fc[c]) / (1.0 + beta), beta);
+  return rc_shape(F - ch.fc[c], 2.0 * ch.hw[c] / (1.0 + beta), beta);
 }
 
 // Laplace transform M(a) = int g(u) exp(-a u) du of the unit-area raised cosine (rectangle: beta = 0):
@@ -300,14 +301,14 @@ struct TileGeo {
 __device__ inline TileGeo tile_geo(const ChanLds& ch, int n, double fnli, int k, double f_ref) {
   TileGeo g;
   g.fi = fnli;
-  g.xp = ch.hi_edge[n - 1] - g.fi;
-  g.xn = g.fi - ch.lo_edge[0];
-  g.slo = ch.lo_edge[k] - g.fi;
-  g.shi = ch.hi_edge[k] - g.fi;
+  g.xp = ch.hi(n - 1) - g.fi;
+  g.xn = g.fi - ch.lo(0);
+  g.slo = ch.lo(k) - g.fi;
+  g.shi = ch.hi(k) - g.fi;
   g.wi = g.fi - f_ref;
   g.gk = ch.psd[k];
-  g.lo0 = ch.lo_edge[0];
-  g.cinv = n > 1 ? (float)((double)(n - 1) / (ch.lo_edge[n - 1] - g.lo0)) : 0.0f;
+  g.lo0 = ch.lo(0);
+  g.cinv = n > 1 ? (float)((double)(n - 1) / (ch.lo(n - 1) - g.lo0)) : 0.0f;
   return g;
 }
 
@@ -363,17 +364,17 @@ __device__ inline int find_channel(const ChanLds& ch, int n, double F, const Til
   int c = (int)((float)(F - g.lo0) * g.cinv);
   c = c < 0 ? 0 : (c > n - 1 ? n - 1 : c);
   int steps = 0;
-  while (c > 0 && ch.lo_edge[c] > F && steps < 4) { --c; ++steps; }
-  while (c + 1 < n && ch.lo_edge[c + 1] <= F && steps < 4) { ++c; ++steps; }
+  while (c > 0 && ch.lo(c) > F && steps < 4) { --c; ++steps; }
+  while (c + 1 < n && ch.lo(c + 1) <= F && steps < 4) { ++c; ++steps; }
   if (steps >= 4) {
     int lo = 0, hi = n;
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
-      if (ch.lo_edge[mid] <= F) lo = mid; else hi = mid;
+      if (ch.lo(mid) <= F) lo = mid; else hi = mid;
     }
     c = lo;
   }
-  return F < ch.hi_edge[c] ? c : -1;
+  return F < ch.hi(c) ? c : -1;
 }
 
 // One node of a part: offsets, channels, interpolation segments, phase rate (revolutions per m).

@@ -311,7 +311,7 @@ struct TileArgs {
 
 // lowrank: room for the tile's f term of the low-rank exponent (FP32 form with the ODE profile only)
 __host__ __device__ inline size_t tile_lds_bytes(int nmax, int gs, int M, bool lowrank) {
-  return sizeof(double) * (4 * (size_t)nmax + 4 * (size_t)gs + 4) + (sizeof(StepLds) + sizeof(Col4)) * (size_t)M +
+  return sizeof(double) * (3 * (size_t)nmax + 4 * (size_t)gs + 4) + (sizeof(StepLds) + sizeof(Col4)) * (size_t)M +
          (lowrank ? sizeof(float) * kRank : 0) + 16;
 }
 
@@ -337,8 +337,8 @@ k_tiles(TileArgs A) {
   extern __shared__ __align__(16) char smem_raw[];
   const int nmax = A.nmax, GS = A.fp.grid_s, GV = A.fp.grid_v, M = A.fp.n_steps, tid = threadIdx.x;
   double* d = reinterpret_cast<double*>(smem_raw);
-  const ChanLds ch{d, d + nmax, d + 2 * nmax, d + 3 * nmax};
-  d += 4 * nmax;
+  const ChanLds ch{d, d + nmax, d + 2 * nmax};
+  d += 3 * nmax;
   const RowLds rw{d, d + GS, d + 2 * GS, d + 3 * GS};
   d += 4 * GS;
   double* red = d;
