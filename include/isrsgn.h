@@ -163,7 +163,10 @@ int isrsgn_snr(isrsgn_fibre* h, const isrsgn_plan* plan, const double* P_w_dev, 
  * keeps no store), and splits the rows into as many batches as that bound needs; it lives
  * until isrsgn_destroy.  If a row does not fit or the allocation fails, the adjoint
  * recomputes S instead (same result, slower).  ISRSGN_ENOMEM if the adjoint's other
- * buffers (O(n_ch_total * n_steps) doubles) cannot be allocated. */
+ * buffers (O(n_ch_total * n_steps) doubles) cannot be allocated.  The FP32 form's adjoint with
+ * the store runs sixteen-wave workgroups where their LDS fits the device (plans up to about
+ * 1400 channels at grid 128 x 128, 112 steps), else four-wave ones; ISRSGN_ADJOINT_WAVES=4 in
+ * the environment at setup keeps four (same result to the rounding of FP64 atomics). */
 int isrsgn_snr_grad(isrsgn_fibre* h, const isrsgn_plan* plan, const double* P_w_dev, const double* nf_lin_dev,
                     double snr_trx_lin, double* snr_dev, double* thr_bps_dev, double* dthr_dP_dev,
                     void* hip_stream);

@@ -788,8 +788,10 @@ const AdjKernel kAdjKernels[2][2][2][2][2][2] = {{ISRSGN_ADJ(0, false), ISRSGN_A
 bool adjoint_split(const FibreParams& fp) { return fp.precision == 0 && fp.profile != 0; }
 
 // Waves per workgroup: sixteen for the FP32 form with the stored S when that layout's LDS fits
+// (unless fp.adj_wide is off), else four
 int adjoint_waves(const FibreParams& fp, int nmax, bool stored, size_t lds_max) {
-  const bool wide = fp.precision == 0 && stored && adjoint_lds_bytes(nmax, fp.grid_s, fp.n_steps, 0, 16) <= lds_max;
+  const bool wide = fp.adj_wide && fp.precision == 0 && stored &&
+                    adjoint_lds_bytes(nmax, fp.grid_s, fp.n_steps, 0, 16) <= lds_max;
   return wide ? 16 : 4;
 }
 

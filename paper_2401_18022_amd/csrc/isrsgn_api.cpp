@@ -876,6 +876,8 @@ int isrsgn_setup_fibre(const isrsgn_fibre_desc* d, isrsgn_fibre** out) {
     const char* lr = std::getenv("ISRSGN_LOWRANK");
     const int cap = lr && *lr ? std::atoi(lr) : kRank;
     fp.lowrank = cap < 0 ? 0 : (cap > kRank ? kRank : cap);
+    const char* aw = std::getenv("ISRSGN_ADJOINT_WAVES");
+    fp.adj_wide = aw && *aw && std::atoi(aw) == 4 ? 0 : 1;
   }
   fp.s_decades = d->s_decades;
   fp.n_tab = d->n_tab;

@@ -37,6 +37,7 @@ struct FibreParams {
   int profile, photon_ratio, n_steps, grid_s, grid_v, ode_sub, precision;
   int n_spans;  // identical spans: phased-array factor per node, n-fold ASE
   int lowrank;  // most terms of the low-rank profile table (kRank; ISRSGN_LOWRANK=N caps it, 0: table reads)
+  int adj_wide;  // the sixteen-wave adjoint where its LDS fits (1; ISRSGN_ADJOINT_WAVES=4 keeps four waves)
   double rolloff;  // raised-cosine roll-off of every transmit spectrum (0: rectangular)
   int nli;         // points of the within-channel NLI rule
   double s_decades;

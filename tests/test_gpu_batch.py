@@ -143,3 +143,29 @@ def test_row_batched_gradient_matches_recompute(prec):
         assert (g - ref[2]).abs().max().item() <= tol * scale, mb
         assert nodes[mb] == nodes["0"], mb
     assert t.equal(snr1, ref[0]) and t.equal(thr1, ref[1])
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("profile,rolloff", [(W.PROFILE_ODE, 0.0), (W.PROFILE_CLOSED_FORM, 0.0), (W.PROFILE_ODE, 0.1)])
+def test_adjoint_four_and_sixteen_wave_workgroups_agree(profile, rolloff):
+    """The FP32 adjoint with the S store runs sixteen-wave workgroups where their LDS fits and
+    four-wave ones otherwise (large plans).  Forced to four (ISRSGN_ADJOINT_WAVES=4) it gives the
+    same gradient to the rounding of the FP64 atomics, and the same SNR bit for bit."""
+    t = torch()
+    wl = W.random_small(48, 7, profile=profile, rolloff=rolloff)
+    P = t.tensor(wl.plan.p_w, dtype=t.float64, device="cuda")
+    nf = t.tensor(wl.plan.nf_lin, dtype=t.float64, device="cuda")
+    res = {}
+    for waves in ("4", "16"):
+        os.environ["ISRSGN_ADJOINT_WAVES"] = waves
+        try:
+            eng = B.Engine(wl.fibre, W.FP32)
+            res[waves] = eng.snr_grad(wl.plan, P, nf)
+            t.cuda.synchronize()
+            assert eng.work_counts()["grad_batches"] >= 1
+        finally:
+            del os.environ["ISRSGN_ADJOINT_WAVES"]
+    a, b = res["4"], res["16"]
+    assert t.equal(a[0], b[0]) and t.equal(a[1], b[1])
+    scale = a[2].abs().max().item()
+    assert (a[2] - b[2]).abs().max().item() <= 1e-12 * scale
