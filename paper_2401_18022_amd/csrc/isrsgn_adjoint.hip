@@ -89,8 +89,11 @@ struct AdjCfg<1> {
 __host__ __device__ inline size_t adjoint_lds_bytes(int nmax, int gs, int M, int prec, int waves) {
   const int mc = prec == 0 ? 16 : 8;
   const size_t rb = prec == 0 ? 4 : 8;
-  // (+1 double: the step tables start on a 16-byte boundary)
-  return sizeof(double) * (3 * (size_t)nmax + 4 * (size_t)gs + (size_t)nmax + 7 * (size_t)M + kAdjWavesMax + 4 + 1) +
+  // doubles: channels (3 nmax), rows (4 gs), the dT/dG histogram (nmax), the hot-channel and
+  // f-term rows (7 M), block_sum's scratch, the low-rank f term (kRank floats) and one to start
+  // the step tables on a 16-byte boundary; then the step tables, staging and metadata
+  return sizeof(double) * (3 * (size_t)nmax + 4 * (size_t)gs + (size_t)nmax + 7 * (size_t)M + kAdjWavesMax +
+                           kRank / 2 + 1) +
          (sizeof(StepLds) + sizeof(Col4)) * (size_t)M + waves * (size_t)mc * stage_row(prec) * rb +
          waves * 7 * kMetaStride * 4 + 16;
 }
@@ -842,7 +845,7 @@ hipError_t launch_adjoint_tiles(const PlanView& pv, const FibreParams& fp, const
   const size_t shm = adjoint_lds_bytes(nmax, fp.grid_s, fp.n_steps, fp.precision, waves);
   // split form: the low-rank instantiation (its own tile counter), then the gather one, which
   // returns at once when every plan of the range has a low-rank table
-  for (int lr = adjoint_split(fp) ? 1 : 0; lr >= 0; --lr) {
+  for (int lr = adjoint_split(fp) && fp.lowrank > 0 ? 1 : 0; lr >= 0; --lr) {
     const void* k = adjoint_kernel(fp, stored, lr != 0, waves);
     if (shm > 65536) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     void* args[] = {&a};
