@@ -120,10 +120,10 @@ __device__ inline void load_q4(const real* p, real* q) {
 //   Re(conj(S) term_m) = |S| amp_m cos 2 pi (phr z_m - th)                  (midpoint forms)
 //                      = |S| p_m [s(z_(m+1/2)) - s(z_(m-1/2))] / (2 pi phr)  (edge form),
 // s(z) = sin 2 pi (phr z - th): one hardware sine or cosine per step instead of both.
-// NodePhase: cqs = cq |S| (the node's factor), th in FP32, hoff = 1/2 - th for the FP64 reduction.
+// NodePhase: cqs = cq |S| (the node's factor), th in FP32, and -th in FP64 for the reduction.
 struct NodePhase {
   float cqs, th;
-  double hoff;
+  double nth;
 };
 
 // arg(x + j y) / (2 pi) in revolutions, FP32: octant reduction to t = min/max in [0, 1], then
@@ -148,9 +148,9 @@ __device__ inline float atan_rev32(float y, float x) {
   return y < 0.0f ? -r : r;
 }
 
-// s(z) at a step edge, the FP64 phase reduced to [-1/2, 1/2) revolutions.
-__device__ inline float edge_sine32(double phr, double z, double hoff) {
-  return __builtin_amdgcn_sinf((float)__builtin_amdgcn_fract(fma(phr, z, hoff)) - 0.5f);
+// s(z) at a step edge, the FP64 phase reduced to [0, 1) revolutions.
+__device__ inline float edge_sine32(double phr, double z, double nth) {
+  return __builtin_amdgcn_sinf((float)__builtin_amdgcn_fract(fma(phr, z, nth)));
 }
 
 template <bool kLinear, int kTier, class Src>
@@ -160,7 +160,7 @@ __device__ inline float term32_proj(const Term32& q, int m, const StepLds* __res
   const float2 cab = col_pair(q, col, m);
   // small form: |phr z_m| < 1/4 and |th| <= 1/2, within the hardware cosine's direct range
   const float fr = kTier == kTierSmall ? fmaf(q.phrf, sv.zmf, -ph.th)
-                                       : (float)__builtin_amdgcn_fract(fma(q.phr, sv.zm, ph.hoff)) - 0.5f;
+                                       : (float)__builtin_amdgcn_fract(fma(q.phr, sv.zm, ph.nth));
   return amp32<kLinear, kTier>(q, m, sv, cab, src) * __builtin_amdgcn_cosf(fr);
 }
 
@@ -192,10 +192,10 @@ __device__ inline void stage_chunk32(const Term32& t, bool valid, const Split32&
     if (xe > pe) stage_range32<kLinear, kTierMixed>(t, m0, pe, xe, ph, st, col, src, out);
     if (m1 > xe) {  // edge form
       const float c = ph.cqs * 0.5f * t.inv_piphr;
-      float s0 = edge_sine32(t.phr, xe > 0 ? st[xe - 1].zu : 0.0, ph.hoff);
+      float s0 = edge_sine32(t.phr, xe > 0 ? st[xe - 1].zu : 0.0, ph.nth);
 #pragma unroll 2
       for (int m = xe; m < m1; ++m) {
-        const float s1 = edge_sine32(t.phr, st[m].zu, ph.hoff);
+        const float s1 = edge_sine32(t.phr, st[m].zu, ph.nth);
         const float p = __builtin_amdgcn_exp2f(log2p32<kLinear>(t, m, col_pair(t, col, m), src));
         out[(m - m0) * kRow32] = c * (p * (s1 - s0));
         s0 = s1;
@@ -429,11 +429,11 @@ k_adjoint(AdjArgs A) {
           }
         }
         real* my_stage = stage + (size_t)wv * MC * kRow;
-        NodePhase ph{0.0f, 0.0f, 0.5};
+        NodePhase ph{0.0f, 0.0f, 0.0};
         if (kPrec == 0 && valid) {
           ph.cqs = (float)((double)cq * sqrt((double)sr * sr + (double)si * si));
           ph.th = atan_rev32((float)si, (float)sr);
-          ph.hoff = 0.5 - (double)ph.th;
+          ph.nth = -(double)ph.th;
         }
         // pass 2 in chunks of MC steps
         for (int m0 = 0; m0 < M; m0 += MC) {

@@ -438,7 +438,7 @@ __device__ inline void node_shapes(const ChanLds& ch, const RowLds& rw, const Ti
 // (re, im).  p_m = exp(E_m), E_m = [ln rho(f1) + ln rho(f2) + ln rho(f3) - ln rho(f_i)] / 2 (eq. pk);
 // with a profile linear in f (the closed form) E_m = ln rho(f3) exactly.
 //
-// FP32 form: the phase phi z_m is formed in FP64 and reduced to [-1/2, 1/2] revolutions before
+// FP32 form: the phase phi z_m is formed in FP64 and reduced to [0, 1) revolutions before
 // the FP32 hardware sine/cosine (which take revolutions); the sinc factor uses its Taylor
 // polynomial while |phi dz_m / 2| < 1/2; E_m comes from an FP32 table of ln rho log2(e)/2.
 // Per-step data of the current plan, staged in LDS and read with uniform addresses.
@@ -657,8 +657,9 @@ __device__ inline float2 term32(const Term32& q, int m, const StepLds* __restric
   if (kTier == kTierSmall) {
     fr = q.phrf * sv.zmf;  // |phr z_m| < 1/4 at every step in this form: already reduced
   } else {
-    // fract(phr z_m + 1/2) - 1/2 lies in [-1/2, 1/2): one FMA, fract and convert in FP64
-    fr = (float)__builtin_amdgcn_fract(fma(q.phr, sv.zm, 0.5)) - 0.5f;
+    // fract(phr z_m) in [0, 1): one product and fract in FP64, then the conversion (the hardware
+    // sine and cosine take any argument within 256 revolutions, equally accurate on [0, 1))
+    fr = (float)__builtin_amdgcn_fract(q.phr * sv.zm);
   }
   const float sn = __builtin_amdgcn_sinf(fr);
   const float cs = __builtin_amdgcn_cosf(fr);
@@ -666,9 +667,9 @@ __device__ inline float2 term32(const Term32& q, int m, const StepLds* __restric
   return make_float2(amp * cs, amp * sn);
 }
 
-// (cos, sin) of 2 pi phr z at a step edge, the FP64 phase reduced to [-1/2, 1/2) revolutions.
+// (cos, sin) of 2 pi phr z at a step edge, the FP64 phase reduced to [0, 1) revolutions.
 __device__ inline float2 edge_phasor32(double phr, double z) {
-  const float fr = (float)__builtin_amdgcn_fract(fma(phr, z, 0.5)) - 0.5f;
+  const float fr = (float)__builtin_amdgcn_fract(phr * z);
   return make_float2(__builtin_amdgcn_cosf(fr), __builtin_amdgcn_sinf(fr));
 }
 

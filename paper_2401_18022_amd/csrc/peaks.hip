@@ -110,6 +110,15 @@ int main() {
   }
   std::printf("revolutions in [-1/2, 1/2): max |sin err| %.2e, max |cos err| %.2e; exp2 on [-20, 20): max rel %.2e\n",
               ws, wc, we);
+  // the same over one full turn [0, 1): the hardware reduces its argument itself
+  for (int i = 0; i < n; ++i) x[i] = (float)i / n;
+  run();
+  ws = wc = 0;
+  for (int i = 0; i < n; ++i) {
+    ws = std::fmax(ws, std::fabs(s[i] - std::sin(2 * M_PI * (double)x[i])));
+    wc = std::fmax(wc, std::fabs(c[i] - std::cos(2 * M_PI * (double)x[i])));
+  }
+  std::printf("revolutions in [0, 1): max |sin err| %.2e, max |cos err| %.2e\n", ws, wc);
   for (int i = 0; i < n; ++i) x[i] = (float)std::pow(10.0, -37.0 + 36.7 * i / (n - 1)) * ((i & 1) ? -1.f : 1.f);
   run();
   for (int dd = -37; dd < 0; dd += 3) {
