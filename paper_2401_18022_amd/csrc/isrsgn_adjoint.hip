@@ -297,7 +297,7 @@ k_adjoint(AdjArgs A) {
       cur_b = b;
     }
     if (kPrec == 0) load_cols<kLinear>(col, A.w.lt32 + (size_t)M * o, n, M, sf, tf, k);
-    if (kLr) lowrank_f_term(A.w.lr_b + (size_t)kRank * o, sf, (float)tf, lr_bf);
+    if (kLr) lowrank_f_term(A.w.lr_b + (size_t)kRank * o, sf, (float)tf, lr_bf);  // (the f term only)
     // FP64 form: the f-term column in the step-table slot (unused by that form)
     double* lf64 = reinterpret_cast<double*>(steps);
     if (kPrec == 1 && !kLinear) load_fcol64(lf64, A.w.ell64 + (size_t)M * o, n, M, sf, tf);
@@ -320,7 +320,9 @@ k_adjoint(AdjArgs A) {
       for (int64_t base = 0; base < nodes; base += kAdjBlock) {
         const int64_t q = base + tid;
         Node nd;
-        const bool valid = q < nodes && make_node(ch, rw, g, n, k, part, (int)(q / GV), (int)(q % GV), A.fp, &nd);
+        // (the FP32 form's segment weights as the forward kernel forms them)
+        const bool valid =
+            q < nodes && make_node<kPrec == 0>(ch, rw, g, n, k, part, (int)(q / GV), (int)(q % GV), A.fp, &nd);
         // raised-cosine shapes at f1, f2, f3 relative to the flat PSDs (1: rectangle)
         double sh1 = 1.0, sh2 = 1.0, sh3 = 1.0;
         if (kRc && valid)
@@ -385,7 +387,10 @@ k_adjoint(AdjArgs A) {
           lsrc.a = const_f32(A.w.lr_a + (size_t)M * kRank * b);
           int sa, sb;
           col_segments(k, n, &sa, &sb);
-          lsrc.setup(t32, A.w.lr_b + (size_t)kRank * o, t32.up3 ? sb : sa, lr_bf);
+          // the f3 segment's row straight from global memory: staging it in LDS like the forward
+          // does moves this kernel's register allocation to more spills and runs slower
+          lsrc.setup<true>(t32, A.w.lr_b + (size_t)kRank * o, A.w.lr_b + (size_t)kRank * (o + (t32.up3 ? sb : sa)),
+                           lr_bf);
         }
         if (valid) {
           if (kStored) {

@@ -249,13 +249,18 @@ __device__ inline double spectrum_md(double a, double R, double beta) {
   return (sd * ch + s * shd) / d - s * ch * (2.0 * ac * c) / (d * d);
 }
 
-// Interpolation segment and weight of ln rho at F, given the channel c that holds F.
+// Interpolation segment and weight of ln rho at F, given the channel c that holds F.  kT32: the
+// weight for the FP32 form, which uses it in FP32 (offset in FP64, then an FP32 quotient).
+template <bool kT32 = false>
 __device__ inline void segment(const ChanLds& ch, int n, int c, double F, int* seg, double* t) {
   if (n == 1) { *seg = 0; *t = 0.0; return; }
   int s = F >= ch.fc[c] ? c : c - 1;
   s = s < 0 ? 0 : (s > n - 2 ? n - 2 : s);
   *seg = s;
-  *t = (F - ch.fc[s]) / (ch.fc[s + 1] - ch.fc[s]);
+  if constexpr (kT32)
+    *t = (double)((float)(F - ch.fc[s]) * __builtin_amdgcn_rcpf((float)(ch.fc[s + 1] - ch.fc[s])));
+  else
+    *t = (F - ch.fc[s]) / (ch.fc[s + 1] - ch.fc[s]);
 }
 
 // The f term of eq. (pk) at the NLI frequency F of COI i (fc: the plan's centres): the centre
@@ -394,6 +399,8 @@ __device__ inline double span_array_factor(double x, int n) {
   return q * q;
 }
 
+// kT32: segment weights for the FP32 form
+template <bool kT32 = false>
 __device__ inline bool make_node(const ChanLds& ch, const RowLds& rw, const TileGeo& g, int n, int k, int part,
                                  int a, int bcol, const FibreParams& fp, Node* nd) {
   const double dv = rw.dv[a];
@@ -412,9 +419,9 @@ __device__ inline bool make_node(const ChanLds& ch, const RowLds& rw, const Tile
   nd->gprod = ch.psd[c1] * ch.psd[c2] * g.gk;
   nd->phr = phase_mismatch(x, y, g.wi, fp.b2, fp.b3, fp.b4) * (0.5 / kPi);
   if (fp.n_spans > 1) nd->w *= span_array_factor(nd->phr * fp.span, fp.n_spans);
-  segment(ch, n, c1, g.fi + x, &nd->s1, &nd->t1);
-  segment(ch, n, c2, g.fi + y, &nd->s2, &nd->t2);
-  segment(ch, n, k, g.fi + x + y, &nd->s3, &nd->t3);
+  segment<kT32>(ch, n, c1, g.fi + x, &nd->s1, &nd->t1);
+  segment<kT32>(ch, n, c2, g.fi + y, &nd->s2, &nd->t2);
+  segment<kT32>(ch, n, k, g.fi + x + y, &nd->s3, &nd->t3);
   return true;
 }
 
@@ -585,17 +592,28 @@ struct LowRank32 {
   // the reads are scalar loads and the factors sit in SGPRs (no LDS traffic, no VGPRs)
   ConstF32* a;
   float c[kRank];
-  // b: the plan's [channel][kRank] (b_r, b_r(next channel) - b_r); f3 lies in segment s3 of the
-  // tile's column pair; bf: the tile's f term b_r at its NLI frequency (LDS, lowrank_f_term)
-  __device__ void setup(const Term32& q, const float2* __restrict__ b, int s3, const float* bf) {
+  // b: the plan's [channel][kRank] (b_r, b_r(next channel) - b_r); b3: the same row of the
+  // node's f3 segment, one of the tile's column pair (LDS); bf: the tile's f term b_r at its NLI
+  // frequency (LDS); both from lowrank_tile_terms
+  // kB3Vec4: b3s is 16-byte aligned (a row of b in global memory), read as float4
+  template <bool kB3Vec4 = false>
+  __device__ void setup(const Term32& q, const float2* __restrict__ b, const float2* b3s, const float* bf) {
     const float4* b1 = reinterpret_cast<const float4*>(b + (size_t)(q.o1 / sizeof(float2)) * kRank);
     const float4* b2 = reinterpret_cast<const float4*>(b + (size_t)(q.o2 / sizeof(float2)) * kRank);
-    const float4* b3 = reinterpret_cast<const float4*>(b + (size_t)s3 * kRank);
 #pragma unroll
     for (int j = 0; j < kRank / 2; ++j) {
-      const float4 u = b1[j], v = b2[j], w = b3[j];
-      c[2 * j] = (fmaf(q.t1, u.y, u.x) + fmaf(q.t2, v.y, v.x)) + (fmaf(q.t3, w.y, w.x) - bf[2 * j]);
-      c[2 * j + 1] = (fmaf(q.t1, u.w, u.z) + fmaf(q.t2, v.w, v.z)) + (fmaf(q.t3, w.w, w.z) - bf[2 * j + 1]);
+      const float4 u = b1[j], v = b2[j];
+      float2 w0, w1;  // (the LDS rows are only 8-byte aligned)
+      if constexpr (kB3Vec4) {
+        const float4 w = reinterpret_cast<const float4*>(b3s)[j];
+        w0 = make_float2(w.x, w.y);
+        w1 = make_float2(w.z, w.w);
+      } else {
+        w0 = b3s[2 * j];
+        w1 = b3s[2 * j + 1];
+      }
+      c[2 * j] = (fmaf(q.t1, u.y, u.x) + fmaf(q.t2, v.y, v.x)) + (fmaf(q.t3, w0.y, w0.x) - bf[2 * j]);
+      c[2 * j + 1] = (fmaf(q.t1, u.w, u.z) + fmaf(q.t2, v.w, v.z)) + (fmaf(q.t3, w1.y, w1.x) - bf[2 * j + 1]);
     }
   }
   // smallest terms first; the same order as the factorisation's FP32 check
@@ -613,12 +631,27 @@ struct LowRank32 {
   }
 };
 
-// The f term of the low-rank exponent for one tile: bf_r = b_r(sf) + tf (b_r(sf + 1) - b_r(sf))
-// (b_r(sf) itself at a channel centre), written to LDS by the first kRank threads.
+// Per-tile terms of the low-rank exponent in LDS, t[5 kRank] (kRank + 2 kRank float2):
+//   t[0, kRank): the f term bf_r = b_r(sf) + tf (b_r(sf + 1) - b_r(sf)) (b_r(sf) itself at a
+//   channel centre); then the rows (b_r, next - b_r) of the tile's two f3 segments A = sa, B = sb.
+// Written by the first 3 kRank threads.
+constexpr int kLrTileFloats = 5 * kRank;
+
+// The f term alone (the first kRank floats of lowrank_tile_terms), by the first kRank threads.
 __device__ inline void lowrank_f_term(const float2* __restrict__ b, int sf, float tf, float* bf) {
   if (threadIdx.x < kRank) {
     const float2 x = b[(size_t)sf * kRank + threadIdx.x];
     bf[threadIdx.x] = tf == 0.0f ? x.x : fmaf(tf, x.y, x.x);
+  }
+}
+__device__ inline void lowrank_tile_terms(const float2* __restrict__ b, int sf, float tf, int sa, int sb, float* t) {
+  const int r = threadIdx.x;
+  if (r < kRank) {
+    const float2 x = b[(size_t)sf * kRank + r];
+    t[r] = tf == 0.0f ? x.x : fmaf(tf, x.y, x.x);
+  } else if (r < 3 * kRank) {
+    const int q = r - kRank;
+    reinterpret_cast<float2*>(t + kRank)[q] = b[(size_t)(q < kRank ? sa : sb) * kRank + q % kRank];
   }
 }
 

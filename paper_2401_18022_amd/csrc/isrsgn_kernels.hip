@@ -309,10 +309,10 @@ struct TileArgs {
   unsigned int t_end;
 };
 
-// lowrank: room for the tile's f term of the low-rank exponent (FP32 form with the ODE profile only)
+// lowrank: room for the tile's terms of the low-rank exponent (FP32 form with the ODE profile only)
 __host__ __device__ inline size_t tile_lds_bytes(int nmax, int gs, int M, bool lowrank) {
   return sizeof(double) * (3 * (size_t)nmax + 4 * (size_t)gs + 4) + (sizeof(StepLds) + sizeof(Col4)) * (size_t)M +
-         (lowrank ? sizeof(float) * kRank : 0) + 16;
+         (lowrank ? sizeof(float) * kLrTileFloats : 0) + 16;
 }
 
 __host__ __device__ inline bool tile_lowrank(const FibreParams& fp) { return fp.precision == 0 && fp.profile != 0; }
@@ -345,8 +345,8 @@ k_tiles(TileArgs A) {
   d += 4;
   StepLds* steps = reinterpret_cast<StepLds*>(d);
   Col4* col = reinterpret_cast<Col4*>(steps + M);
-  float* lr_bf = reinterpret_cast<float*>(col + M);  // [kRank]: the tile's f term of the low-rank exponent
-  unsigned int* tile_slot = reinterpret_cast<unsigned int*>(lr_bf + (kPrec == 0 && !kLinear ? kRank : 0));
+  float* lr_t = reinterpret_cast<float*>(col + M);  // the tile's low-rank terms (lowrank_tile_terms)
+  unsigned int* tile_slot = reinterpret_cast<unsigned int*>(lr_t + (kPrec == 0 && !kLinear ? kLrTileFloats : 0));
   const PlanView& pv = A.pv;
   int cur_b = -1, cur_lr = -1;
   for (;;) {
@@ -375,7 +375,11 @@ k_tiles(TileArgs A) {
     // FP64 form: the f-term column in the step-table slot (unused by that form)
     double* lf64 = reinterpret_cast<double*>(steps);
     if (kPrec == 1 && !kLinear) load_fcol64(lf64, A.w.ell64 + (size_t)M * o, n, M, sf, tf);
-    if (kPrec == 0 && !kLinear && cur_lr >= 0) lowrank_f_term(A.w.lr_b + (size_t)kRank * o, sf, (float)tf, lr_bf);
+    if (kPrec == 0 && !kLinear && cur_lr >= 0) {
+      int sa, sb;
+      col_segments(k, n, &sa, &sb);
+      lowrank_tile_terms(A.w.lr_b + (size_t)kRank * o, sf, (float)tf, sa, sb, lr_t);
+    }
     __syncthreads();
     const TileGeo g = uniform_geo(tile_geo(ch, n, fnli, k, A.fp.f_ref));
     double acc = 0.0;
@@ -388,7 +392,8 @@ k_tiles(TileArgs A) {
       for (int64_t base = 0; base < nodes; base += kTileBlock) {
         const int64_t q = base + tid;
         Node nd;
-        const bool valid = q < nodes && make_node(ch, rw, g, n, k, part, (int)(q / GV), (int)(q % GV), A.fp, &nd);
+        const bool valid =
+            q < nodes && make_node<kPrec == 0>(ch, rw, g, n, k, part, (int)(q / GV), (int)(q % GV), A.fp, &nd);
         double s2v;
         if (kPrec == 0) {
           Term32 tq{};
@@ -399,9 +404,8 @@ k_tiles(TileArgs A) {
           if (!kLinear && cur_lr >= 0) {
             LowRank32 src;
             src.a = const_f32(A.w.lr_a + (size_t)M * kRank * b);
-            int sa, sb;
-            col_segments(k, n, &sa, &sb);
-            src.setup(tq, A.w.lr_b + (size_t)kRank * o, tq.up3 ? sb : sa, lr_bf);
+            src.setup(tq, A.w.lr_b + (size_t)kRank * o, reinterpret_cast<const float2*>(lr_t + kRank) + (tq.up3 ? kRank : 0),
+                      lr_t);
             accumulate32<kLinear, kUnroll>(tq, sp, steps, col, src, M, &sr, &si);
           } else {
             const Gather32 src{make_tab32(A.w.lt32 + (size_t)M * o, n, M), n};
