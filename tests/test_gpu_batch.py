@@ -169,3 +169,35 @@ def test_adjoint_four_and_sixteen_wave_workgroups_agree(profile, rolloff):
     assert t.equal(a[0], b[0]) and t.equal(a[1], b[1])
     scale = a[2].abs().max().item()
     assert (a[2] - b[2]).abs().max().item() <= 1e-12 * scale
+
+
+@pytest.mark.gpu
+def test_adjoint_mixed_lowrank_and_gather_plans():
+    """FP32 form with the ODE profile: the adjoint's low-rank instantiation takes the tiles of plans
+    that have a low-rank profile table, the gather instantiation the others.  Capping the rank
+    (ISRSGN_LOWRANK=N) below what some plans of a batch need leaves a mix in one launch; SNR and
+    gradient then agree with the table reads everywhere (ISRSGN_LOWRANK=0)."""
+    t = torch()
+    wl = W.config_batch(n_profiles=12, grid_s=12, grid_v=12, n_steps=24)
+    P = t.tensor(wl.plan.p_w, dtype=t.float64, device="cuda")
+    nf = t.tensor(wl.plan.nf_lin, dtype=t.float64, device="cuda")
+    res, plans = {}, {}
+    for cap in ("0", "2", "3", "4", "5", "6", "7", "8"):
+        os.environ["ISRSGN_LOWRANK"] = cap
+        try:
+            eng = B.Engine(wl.fibre, W.FP32)
+            res[cap] = eng.snr_grad(wl.plan, P, nf)
+            t.cuda.synchronize()
+            plans[cap] = eng.work_counts()["lowrank_plans"]
+        finally:
+            del os.environ["ISRSGN_LOWRANK"]
+    print(f"[mixed] low-rank plans by cap: {plans} of {wl.plan.n_batch}", flush=True)
+    assert plans["0"] == 0
+    mixed = [c for c in plans if 0 < plans[c] < wl.plan.n_batch]
+    assert mixed, plans
+    ref = res["0"]
+    scale = ref[2].abs().max().item()
+    for c in mixed + ["8"]:
+        snr_db = 10 * t.log10(res[c][0] / ref[0])
+        assert snr_db.abs().max().item() <= 1e-5
+        assert (res[c][2] - ref[2]).abs().max().item() <= 1e-5 * scale
