@@ -276,6 +276,10 @@ def main():
                      "traffic_source": rec[2] if rec else None, "kernel": dominant,
                      "kernel_ms_per_step": dom_ms, "launches_per_step": launches,
                      "node_steps_per_step": node_steps, "slots_per_node_step": dom_slots,
+                     "work_count": "formula issue slots per node-step of eq. slow_vary (a transcendental "
+                                   "counted as 4 FP32 slots), not the instructions the kernel issues",
+                     "traffic_note": ("fabric bytes from rocprofv3 FETCH_SIZE/WRITE_SIZE per launch, mostly the "
+                                      "write-back and reload of register spills in the node set-up") if rec else None,
                      "tile_variant": work["variant"]},
         "cpu_baseline": cpu,
         "stages_ms": {k: v / args.steps for k, v in stages.items()},
