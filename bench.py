@@ -87,6 +87,10 @@ def parse():
     ap.add_argument("--fp64-calls", type=int, default=3, help="timed calls of the FP64 form (median reported)")
     ap.add_argument("--cpu-pairs", type=int, default=48,
                     help="interferers per seeded COI in the CPU-oracle sample (16 seeded COIs)")
+    ap.add_argument("--rolloff", type=float, default=0.0,
+                    help="raised-cosine roll-off of every transmit spectrum (0: rectangular)")
+    ap.add_argument("--nli-points", type=int, default=1,
+                    help="points of the within-channel NLI rule per COI (1: the COI centre)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device to device (calibrates rocprofv3 byte counters)")
     return ap.parse_args()
@@ -116,6 +120,9 @@ def main():
     else:
         wl = W.config_batch()
         args.grid = wl.fibre.grid_s
+    spectra = args.rolloff > 0.0 or args.nli_points > 1
+    if spectra:
+        wl = wl.replace_fibre(rolloff=args.rolloff, nli_points=args.nli_points)
     n = len(wl.plan.f_hz)
     offs = np.asarray(wl.plan.offsets)
     pairs = int(np.sum(np.diff(offs) ** 2))
@@ -186,7 +193,7 @@ def main():
     # stage times are sums over the call's launches of the kernel (one per batch of COI rows)
     launches = max(1, work["grad_batches"]) if grad else 1
     achieved = node_steps * dom_slots * FLOP_EQ_PER_SLOT / (dom_ms * 1e-3) / 1e12
-    rec = recorded_traffic(dominant, args.grid) if args.workload == "ou" else None
+    rec = recorded_traffic(dominant, args.grid) if args.workload == "ou" and not spectra else None
 
     fp64 = None
     if not args.no_fp64 and args.workload == "ou" and args.fp64_calls > 0:
@@ -249,6 +256,9 @@ def main():
                                 f"(the work per tile is the same on average; labelled estimate, not measured)"}
 
     what = ("SNR + adjoint gradient" if grad else "SNR (forward) only")
+    if spectra:
+        what += f"; raised-cosine spectra, roll-off {args.rolloff:g}, {args.nli_points} NLI point(s) per COI"
+
     if args.workload == "ou":
         workload = (f"O-to-U 589x96GBaud 100GHz 1260-1675nm, 80 km SSMF, ODE ISRS profile, "
                     f"G={args.grid}x{args.grid}, N_M={wl.fibre.n_steps}, FP32 form, " + what)

@@ -631,8 +631,9 @@ const TileKernel kTileKernels[2][2][kTileVariants] = {{ISRSGN_TILE_VARIANTS(0, f
                                                      {ISRSGN_TILE_VARIANTS(1, false), ISRSGN_TILE_VARIANTS(1, true)}};
 const char* const kTileVariantNames[kTileVariants] = {"unroll1", "unroll2", "unroll2-w5", "unroll1-w4", "unroll2-w4",
                                                        "unroll4-w3"};
-// raised-cosine spectra: one kernel (unroll 2, no occupancy hint) for every variant index
-const TileKernel kTileKernelsRc[2][2] = {{k_tiles<0, false, 2, 0, true>, k_tiles<0, true, 2, 0, true>},
+// raised-cosine spectra: one kernel for every variant index (unroll 2; the FP32 form at least 5
+// waves per SIMD like the rectangular kernels' usual pick, the FP64 form with no occupancy hint)
+const TileKernel kTileKernelsRc[2][2] = {{k_tiles<0, false, 2, 5, true>, k_tiles<0, true, 2, 5, true>},
                                          {k_tiles<1, false, 2, 0, true>, k_tiles<1, true, 2, 0, true>}};
 
 TileKernel tile_kernel(const FibreParams& fp, int variant) {
