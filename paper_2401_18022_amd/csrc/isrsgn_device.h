@@ -447,7 +447,8 @@ __device__ inline void node_shapes(const ChanLds& ch, const RowLds& rw, const Ti
 //
 // FP32 form: the phase phi z_m is formed in FP64 and reduced to [0, 1) revolutions before
 // the FP32 hardware sine/cosine (which take revolutions); the sinc factor uses its Taylor
-// polynomial while |phi dz_m / 2| < 1/2; E_m comes from an FP32 table of ln rho log2(e)/2.
+// polynomial while |phi dz_m / 2| < 1/2 and the edge form beyond; E_m comes from an FP32 table of
+// ln rho log2(e)/2 (Gather32) or from its low-rank form (LowRank32).
 // Per-step data of the current plan, staged in LDS and read with uniform addresses.
 struct StepLds {
   double zm;   // step midpoint z_m
