@@ -471,10 +471,9 @@ k_adjoint(AdjArgs A) {
             // a = sum q, ah = sum q t; the segment's lower channel gets a - ah, the upper ah
             real a1 = 0, a1h = 0, a2 = 0, a2h = 0, qs = 0, x3a = 0, x3c = 0;
             auto put = [=](int c, double v) {
-              int hs = -1;
-#pragma unroll
-              for (int q = 5; q >= 0; --q)
-                if (hot[q] == c) hs = q;
+              // the hot rows: k-1, k, k+1 (rows 0-2), then i-1, i, i+1 (rows 3-5); the first wins
+              const unsigned dk = (unsigned)(c - k + 1), di = (unsigned)(c - i + 1);
+              const int hs = dk < 3u ? (int)dk : (di < 3u ? 3 + (int)di : -1);
               // distinct scopes keep the LDS and global adds apart (no flat atomic)
               if (hs >= 0) __hip_atomic_fetch_add(&tacc[hs * M + m], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
               else __hip_atomic_fetch_add(&gL[(size_t)c * M + m], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
