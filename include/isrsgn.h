@@ -159,9 +159,9 @@ int isrsgn_snr(isrsgn_fibre* h, const isrsgn_plan* plan, const double* P_w_dev, 
  * Workspace: the forward keeps S of eq. (psi_fin) per integration node (8 bytes per node in
  * the FP32 form, 16 in the FP64 form) for one batch of COI rows at a time, so the adjoint
  * does not evaluate the step terms twice.  The handle allocates it per plan on the first
- * gradient call for that plan, at most ISRSGN_STORE_MB MiB (environment, default 16384; 0
- * keeps no store), and splits the rows into as many batches as that bound needs; it lives
- * until isrsgn_destroy.  If a row does not fit or the allocation fails, the adjoint
+ * gradient call for that plan, at most ISRSGN_STORE_MB MiB (environment; 0 keeps no store;
+ * by default half of the device memory free at that call), and splits the rows into as many
+ * batches as that bound needs; it lives until isrsgn_destroy.  If a row does not fit or the allocation fails, the adjoint
  * recomputes S instead (same result, slower).  ISRSGN_ENOMEM if the adjoint's other
  * buffers (O(n_ch_total * n_steps) doubles) cannot be allocated.  The FP32 form's adjoint with
  * the store runs sixteen-wave workgroups where their LDS fits the device (plans up to about
@@ -225,7 +225,7 @@ int isrsgn_stage_times(isrsgn_fibre* h, double* ms_out, int n);
  * autotuner chose (ISRSGN_TILE_VARIANT in the environment forces one; ISRSGN_TUNE_CACHE
  * names a file that keeps the choices across processes), [4] batches of COI rows of a
  * gradient with the per-node store (0: the adjoint recomputed S; the store is bounded by
- * ISRSGN_STORE_MB in the environment, default 16384 MiB, 0 disables it), [5] plans whose FP32
+ * ISRSGN_STORE_MB in the environment, by default half of the free device memory, 0 disables it), [5] plans whose FP32
  * step terms used the low-rank form of the ODE profile table (the rest read the table), [6] the
  * most terms any of them needed.  n is the capacity of out (up to 7). */
 int isrsgn_work_counts(isrsgn_fibre* h, double* out, int n);

@@ -90,12 +90,12 @@ __host__ __device__ inline size_t adjoint_lds_bytes(int nmax, int gs, int M, int
   const int mc = prec == 0 ? 16 : 8;
   const size_t rb = prec == 0 ? 4 : 8;
   // doubles: channels (3 nmax), rows (4 gs), the dT/dG histogram (nmax), the hot-channel and
-  // f-term rows (7 M), block_sum's scratch, the low-rank f term (kRank floats) and one to start
-  // the step tables on a 16-byte boundary; then the step tables, staging and metadata
+  // f-term rows (7 M), block_sum's scratch, the low-rank f term (kRank floats), one to start the
+  // column tables on a 16-byte boundary and the FP64 form's f-term column (M, rounded up to even);
+  // then the f3 columns, staging and metadata
   return sizeof(double) * (3 * (size_t)nmax + 4 * (size_t)gs + (size_t)nmax + 7 * (size_t)M + kAdjWavesMax +
-                           kRank / 2 + 1) +
-         (sizeof(StepLds) + sizeof(Col4)) * (size_t)M + waves * (size_t)mc * stage_row(prec) * rb +
-         waves * 7 * kMetaStride * 4 + 16;
+                           kRank / 2 + 1 + (size_t)((M + 1) & ~1)) +
+         sizeof(Col4) * (size_t)M + waves * (size_t)mc * stage_row(prec) * rb + waves * 7 * kMetaStride * 4 + 16;
 }
 
 constexpr int kRow32 = stage_row(0);
@@ -154,9 +154,9 @@ __device__ inline float edge_sine32(double phr, double z, double nth) {
 }
 
 template <bool kLinear, int kTier, class Src>
-__device__ inline float term32_proj(const Term32& q, int m, const StepLds* __restrict__ st,
+__device__ inline float term32_proj(const Term32& q, int m, ConstStep* __restrict__ st,
                                     const Col4* __restrict__ col, const Src& src, const NodePhase& ph) {
-  const StepLds sv = st[m];
+  const StepRec sv = step_at(st, m);
   const float2 cab = col_pair(q, col, m);
   // small form: |phr z_m| < 1/4 and |th| <= 1/2, within the hardware cosine's direct range
   const float fr = kTier == kTierSmall ? fmaf(q.phrf, sv.zmf, -ph.th)
@@ -168,7 +168,7 @@ __device__ inline float term32_proj(const Term32& q, int m, const StepLds* __res
 // form of the wave's range it falls in (zero past the last step).
 template <bool kLinear, int kTier, class Src>
 __device__ inline void stage_range32(const Term32& t, int m0, int ma, int mb, const NodePhase& ph,
-                                     const StepLds* __restrict__ st, const Col4* __restrict__ col, const Src& src,
+                                     ConstStep* __restrict__ st, const Col4* __restrict__ col, const Src& src,
                                      float* out) {
 #pragma unroll 2
   for (int m = ma; m < mb; ++m) out[(m - m0) * kRow32] = ph.cqs * term32_proj<kLinear, kTier>(t, m, st, col, src, ph);
@@ -176,7 +176,7 @@ __device__ inline void stage_range32(const Term32& t, int m0, int ma, int mb, co
 
 template <bool kLinear, int MC, class Src>
 __device__ inline void stage_chunk32(const Term32& t, bool valid, const Split32& sp, int m0, int M, const NodePhase& ph,
-                                     const StepLds* __restrict__ st, const Col4* __restrict__ col, const Src& src,
+                                     ConstStep* __restrict__ st, const Col4* __restrict__ col, const Src& src,
                                      float* out) {
   if (!valid) {  // one branch per chunk, not per step
 #pragma unroll
@@ -246,9 +246,10 @@ k_adjoint(AdjArgs A) {
   d += kAdjWavesMax;
   float* lr_bf = reinterpret_cast<float*>(d);  // [kRank]: the tile's f term of the low-rank exponent
   d += kRank / 2;
-  d += (d - reinterpret_cast<double*>(smem_raw)) & 1;  // 16-byte boundary for the step tables
-  StepLds* steps = reinterpret_cast<StepLds*>(d);
-  Col4* col = reinterpret_cast<Col4*>(steps + M);
+  d += (d - reinterpret_cast<double*>(smem_raw)) & 1;  // 16-byte boundary for the column tables
+  double* lf64 = d;  // [M]: the FP64 form's f-term column
+  d += (M + 1) & ~1;
+  Col4* col = reinterpret_cast<Col4*>(d);
   constexpr int kRow = stage_row(kPrec);
   real* stage = reinterpret_cast<real*>(col + M);  // [waves][MC][kRow]
   int* meta0 = reinterpret_cast<int*>(stage + kAdjWaves * MC * kRow);
@@ -293,13 +294,13 @@ k_adjoint(AdjArgs A) {
     }
     if (b != cur_b) {
       load_channels(ch, pv, A.P, o, n, A.fp.rolloff);
-      if (kPrec == 0) load_steps(steps, A.w.zm + (size_t)b * M, A.w.dz + (size_t)b * M, A.w.hdz32 + (size_t)b * M, M);
       cur_b = b;
     }
+    // (kLr reads no columns, but skipping the load moves the register allocation to more spills)
     if (kPrec == 0) load_cols<kLinear>(col, A.w.lt32 + (size_t)M * o, n, M, sf, tf, k);
     if (kLr) lowrank_f_term(A.w.lr_b + (size_t)kRank * o, sf, (float)tf, lr_bf);  // (the f term only)
-    // FP64 form: the f-term column in the step-table slot (unused by that form)
-    double* lf64 = reinterpret_cast<double*>(steps);
+    // the plan's step records: wave-uniform reads through scalar loads
+    ConstStep* stc = (ConstStep*)(A.w.step_rec + (size_t)4 * M * b);
     if (kPrec == 1 && !kLinear) load_fcol64(lf64, A.w.ell64 + (size_t)M * o, n, M, sf, tf);
     for (int c = tid; c < n; c += kAdjBlock) gGl[c] = 0.0;
     for (int q = tid; q < 7 * M; q += kAdjBlock) tacc[q] = 0.0;
@@ -378,7 +379,7 @@ k_adjoint(AdjArgs A) {
         Term64 t64;
         if (valid && kPrec == 0) t32 = term32_setup(nd, k, n);
         Split32 sp{};
-        if (kPrec == 0) sp = wave_split(valid, t32, steps, M);
+        if (kPrec == 0) sp = wave_split(valid, t32, stc, M);
         // the exponent of the FP32 form: the f1 + f2 profile terms by table gathers, or the whole
         // exponent from the low-rank table (its step factors through scalar loads)
         const Gather32 gsrc{make_tab32(A.w.lt32 + (size_t)M * o, n, M), n};
@@ -407,8 +408,8 @@ k_adjoint(AdjArgs A) {
             if (kPrec == 1) t64 = term64_setup(nd);
           } else if (kPrec == 0) {
             float a32, b32;
-            if constexpr (kLr) accumulate32<kLinear, 4>(t32, sp, steps, col, lsrc, M, &a32, &b32);
-            else accumulate32<kLinear, 4>(t32, sp, steps, col, gsrc, M, &a32, &b32);
+            if constexpr (kLr) accumulate32<kLinear, 4>(t32, sp, stc, col, lsrc, M, &a32, &b32);
+            else accumulate32<kLinear, 4>(t32, sp, stc, col, gsrc, M, &a32, &b32);
             sr = a32;
             si = b32;
           } else {
@@ -445,9 +446,9 @@ k_adjoint(AdjArgs A) {
           if (kPrec == 0) {
             float* out = reinterpret_cast<float*>(my_stage) + lane;
             if constexpr (kLr)
-              stage_chunk32<kLinear, MC>(t32, valid, sp, m0, M, ph, steps, col, lsrc, out);
+              stage_chunk32<kLinear, MC>(t32, valid, sp, m0, M, ph, stc, col, lsrc, out);
             else
-              stage_chunk32<kLinear, MC>(t32, valid, sp, m0, M, ph, steps, col, gsrc, out);
+              stage_chunk32<kLinear, MC>(t32, valid, sp, m0, M, ph, stc, col, gsrc, out);
           } else {
             for (int mm = 0; mm < MC; ++mm) {
               const int m = m0 + mm;

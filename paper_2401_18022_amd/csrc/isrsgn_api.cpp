@@ -89,7 +89,7 @@ struct PlanEntry {
   int64_t n_tiles = 0;
   DevBuf d_off, d_toff, d_f, d_R, d_alpha, d_aeff, d_gamma, d_cr, d_fpt, d_wpt;
   // workspace
-  DevBuf abar, zm, dz, hdz32, ell64, lt32, ellL, tiles, pnli, snr, counter;
+  DevBuf abar, zm, dz, hdz32, step_rec, ell64, lt32, ellL, tiles, pnli, snr, counter;
   DevBuf lr_a, lr_b, lr_rank, lr_res, lr_b64;  // low-rank form of lt32 (FP32 form, ODE profile)
   DevBuf states, state_off, lam, gG, gL, gLL, gP, coef;
   bool grad_ready = false;
@@ -128,6 +128,7 @@ struct PlanEntry {
     w.zm = zm.as<double>();
     w.dz = dz.as<double>();
     w.hdz32 = hdz32.as<float>();
+    w.step_rec = step_rec.as<double>();
     w.ell64 = ell64.as<double>();
     w.lt32 = lt32.as<float2>();
     w.lr_a = lr_a.as<float>();
@@ -309,7 +310,7 @@ int get_plan(isrsgn_fibre* h, const isrsgn_plan* p, hipStream_t s, PlanEntry** o
             e->d_f.ensure(8 * nt) && e->d_R.ensure(8 * nt) && e->d_alpha.ensure(8 * nt) && e->d_aeff.ensure(8 * nt) &&
             e->d_gamma.ensure(8 * nt) && e->d_cr.ensure(8 * nt) && e->d_fpt.ensure(8 * nt * e->nli) &&
             e->d_wpt.ensure(8 * nt * e->nli) && e->abar.ensure(8 * nb) &&
-            e->zm.ensure(8 * nb * M) && e->dz.ensure(8 * nb * M) && e->hdz32.ensure(4 * nb * M) &&
+            e->zm.ensure(8 * nb * M) && e->dz.ensure(8 * nb * M) && e->hdz32.ensure(4 * nb * M) && e->step_rec.ensure(32 * nb * M) &&
             e->ell64.ensure(8 * nt * M) && e->ellL.ensure(8 * nt) && e->tiles.ensure(8 * (size_t)ntiles) &&
             e->pnli.ensure(8 * nt) && e->snr.ensure(8 * nt) && e->counter.ensure(64) &&
             (h->desc.precision != ISRSGN_FP32 || e->lt32.ensure(8 * nt * M)) &&
@@ -507,13 +508,25 @@ int ensure_grad_workspace(isrsgn_fibre* h, PlanEntry* e) {
   if (err != hipSuccess) return hip_fail(err, "state offsets");
   // The forward pass keeps S of every node for the adjoint (8 B per node in the FP32 form, 16 B
   // in the FP64 form), one batch of complete COI rows at a time (a row's SNR, and so its
-  // upstream weight, needs only that row).  The store is bounded by ISRSGN_STORE_MB (default
-  // 16384 MiB; 0 disables it); when a row does not fit or the allocation fails, the adjoint
-  // recomputes S instead.
+  // upstream weight, needs only that row).  The store is bounded by ISRSGN_STORE_MB (0 disables
+  // it), by default half of the device memory free at this point (one batch for a 589-channel
+  // plan at G=128 on an idle 288 GB device); when a row does not fit or the allocation fails, the
+  // adjoint recomputes S instead.
   e->batches.clear();
   e->store_ok = false;
   const char* env = std::getenv("ISRSGN_STORE_MB");
-  const double store_mb = env && *env ? std::atof(env) : 16384.0;
+  double store_mb = 0.0;
+  if (env && *env) {
+    store_mb = std::atof(env);
+  } else {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
+      store_mb = 0.5 * (double)free_b / 1048576.0;
+    } else {
+      (void)hipGetLastError();
+      store_mb = 16384.0;
+    }
+  }
   const int64_t per_tile = (int64_t)3 * h->desc.grid_s * h->desc.grid_v *
                            (int64_t)(h->desc.precision == ISRSGN_FP32 ? sizeof(float2) : sizeof(double2));
   const int64_t max_tiles = store_mb > 0 ? (int64_t)(store_mb * 1048576.0 / (double)per_tile) : 0;
@@ -775,6 +788,7 @@ size_t carve_noalloc(const isrsgn_fibre* h, int nb, int nt, int64_t ntiles, uint
   w->zm = reinterpret_cast<double*>(take(8 * b * M));
   w->dz = reinterpret_cast<double*>(take(8 * b * M));
   w->hdz32 = reinterpret_cast<float*>(take(4 * b * M));
+  w->step_rec = reinterpret_cast<double*>(take(32 * b * M));
   w->ell64 = reinterpret_cast<double*>(take(8 * n * M));
   if (fp32) w->lt32 = reinterpret_cast<float2*>(take(8 * n * M));
   if (lr) {

@@ -449,8 +449,10 @@ __device__ inline void node_shapes(const ChanLds& ch, const RowLds& rw, const Ti
 // the FP32 hardware sine/cosine (which take revolutions); the sinc factor uses its Taylor
 // polynomial while |phi dz_m / 2| < 1/2 and the edge form beyond; E_m comes from an FP32 table of
 // ln rho log2(e)/2 (Gather32) or from its low-rank form (LowRank32).
-// Per-step data of the current plan, staged in LDS and read with uniform addresses.
-struct StepLds {
+// Per-step data of a plan, read with wave-uniform addresses.  k_steps writes the plan's records to
+// global memory; the forward tile kernel stages them in LDS, and the adjoint reads the global copy
+// through the constant address space (scalar loads into SGPRs, no VGPRs or LDS traffic).
+struct StepRec {
   double zm;   // step midpoint z_m
   double zu;   // upper edge z_m + dz_m / 2 (the lower edge of step 0 is z = 0)
   float hdz;   // dz_m / 2
@@ -458,6 +460,33 @@ struct StepLds {
   float dz;    // dz_m
   float c2;    // (2 pi dz_m / 2)^2: the sinc argument squared is phr^2 c2
 };
+
+__host__ __device__ inline StepRec step_record(double zm, double dz, float hdz) {
+  StepRec v;
+  v.zm = zm;
+  v.zu = zm + 0.5 * dz;
+  v.hdz = hdz;
+  v.zmf = (float)zm;
+  v.dz = 2.0f * hdz;
+  const float c = 2.0f * (float)kPi * hdz;
+  v.c2 = c * c;
+  return v;
+}
+
+// Step m from the LDS copy or from the global one (field by field: no copy constructor binds to
+// the constant address space); the step functions below take either pointer kind (SP).
+using ConstStep = const __attribute__((address_space(4))) StepRec;
+__device__ inline StepRec step_at(const StepRec* st, int m) { return st[m]; }
+__device__ inline StepRec step_at(ConstStep* st, int m) {
+  StepRec v;
+  v.zm = st[m].zm;
+  v.zu = st[m].zu;
+  v.hdz = st[m].hdz;
+  v.zmf = st[m].zmf;
+  v.dz = st[m].dz;
+  v.c2 = st[m].c2;
+  return v;
+}
 
 // Per-tile table columns for the f3 and f_i terms of E_m, staged in LDS.  f3 lies in channel k,
 // so its interpolation segment is A = clamp(k-1) or B = clamp(k); per step:
@@ -516,19 +545,9 @@ __device__ inline void load_cols(Col4* col, const float2* __restrict__ tab, int 
   }
 }
 
-__device__ inline void load_steps(StepLds* st, const double* __restrict__ zm, const double* __restrict__ dz,
+__device__ inline void load_steps(StepRec* st, const double* __restrict__ zm, const double* __restrict__ dz,
                                   const float* __restrict__ hdz, int M) {
-  for (int m = threadIdx.x; m < M; m += blockDim.x) {
-    StepLds v;
-    v.zm = zm[m];
-    v.zu = zm[m] + 0.5 * dz[m];
-    v.hdz = hdz[m];
-    v.zmf = (float)zm[m];
-    v.dz = 2.0f * hdz[m];
-    const float c = 2.0f * (float)kPi * hdz[m];
-    v.c2 = c * c;
-    st[m] = v;
-  }
+  for (int m = threadIdx.x; m < M; m += blockDim.x) st[m] = step_record(zm[m], dz[m], hdz[m]);
 }
 
 // The plan's FP32 profile table [m][c] (float2: scaled ln rho and the slope to the next
@@ -671,7 +690,7 @@ __device__ inline float2 col_pair(const Term32& q, const Col4* __restrict__ col,
 
 // Amplitude of step m's term in the midpoint forms: p_m dz_m sinc(phi dz_m / 2).
 template <bool kLinear, int kTier, class Src>
-__device__ inline float amp32(const Term32& q, int m, const StepLds& sv, float2 cab, const Src& src) {
+__device__ inline float amp32(const Term32& q, int m, const StepRec& sv, float2 cab, const Src& src) {
   const float u2 = q.phrf2 * sv.c2;
   float amp0 = sv.dz * fmaf(u2, fmaf(u2, fmaf(u2, -1.0f / 5040.0f, 1.0f / 120.0f), -1.0f / 6.0f), 1.0f);
   if (kTier == kTierMixed) {  // both forms, then a per-lane select (no branch)
@@ -682,10 +701,10 @@ __device__ inline float amp32(const Term32& q, int m, const StepLds& sv, float2 
   return __builtin_amdgcn_exp2f(log2p32<kLinear>(q, m, cab, src)) * amp0;
 }
 
-template <bool kLinear, int kTier, class Src>
-__device__ inline float2 term32(const Term32& q, int m, const StepLds* __restrict__ st, const Col4* __restrict__ col,
+template <bool kLinear, int kTier, class Src, class SP>
+__device__ inline float2 term32(const Term32& q, int m, SP st, const Col4* __restrict__ col,
                                 const Src& src) {
-  const StepLds sv = st[m];
+  const StepRec sv = step_at(st, m);
   const float2 cab = col_pair(q, col, m);
   float fr;
   if (kTier == kTierSmall) {
@@ -708,14 +727,15 @@ __device__ inline float2 edge_phasor32(double phr, double z) {
 }
 
 // Phasor at the lower edge of step m.
-__device__ inline float2 lower_edge_phasor32(double phr, const StepLds* __restrict__ st, int m) {
+template <class SP>
+__device__ inline float2 lower_edge_phasor32(double phr, SP st, int m) {
   return m > 0 ? edge_phasor32(phr, st[m - 1].zu) : make_float2(1.0f, 0.0f);
 }
 
 // Step m in edge form, as 2 pi phr times its term: p_m (E_(m+1) - E_m) / j.  e holds E_m on
 // entry and E_(m+1) on return.
-template <bool kLinear, class Src>
-__device__ inline float2 term32_edge(const Term32& q, int m, const StepLds* __restrict__ st,
+template <bool kLinear, class Src, class SP>
+__device__ inline float2 term32_edge(const Term32& q, int m, SP st,
                                      const Col4* __restrict__ col, const Src& src, float2& e) {
   const double zu = st[m].zu;
   const float2 cab = col_pair(q, col, m);
@@ -727,7 +747,8 @@ __device__ inline float2 term32_edge(const Term32& q, int m, const StepLds* __re
 }
 
 // First sine step m_s of a node (M if none): the same test as the mixed form's select.
-__device__ inline int sine_step(const Term32& q, const StepLds* __restrict__ st, int M) {
+template <class SP>
+__device__ inline int sine_step(const Term32& q, SP st, int M) {
   if (q.phrf2 * st[0].c2 >= 0.25f) return 0;
   if (q.phrf2 * st[M - 1].c2 < 0.25f) return M;
   int lo = 1, hi = M - 1;  // the answer lies in [1, M - 1]
@@ -740,7 +761,8 @@ __device__ inline int sine_step(const Term32& q, const StepLds* __restrict__ st,
 }
 
 // Whether a node qualifies for the FP32-phase form (plan's last step: largest z and dz).
-__device__ inline bool node_small(const Term32& q, const StepLds* st, int M) {
+template <class SP>
+__device__ inline bool node_small(const Term32& q, SP st, int M) {
   const float ap = fabsf(q.phrf), tp = 2.0f * (float)kPi;
   return ap * st[M - 1].zmf < 0.25f && tp * ap * st[M - 1].hdz < 0.5f;
 }
@@ -752,7 +774,8 @@ struct Split32 {
   int m_lo, m_hi;  // 0 <= m_lo <= m_hi <= M
 };
 
-__device__ inline Split32 wave_split(bool active, const Term32& q, const StepLds* st, int M) {
+template <class SP>
+__device__ inline Split32 wave_split(bool active, const Term32& q, SP st, int M) {
   Split32 r;
   r.small = __all(!active || node_small(q, st, M));
   if (r.small) {
@@ -776,8 +799,8 @@ __device__ inline Split32 wave_split(bool active, const Term32& q, const StepLds
 }
 
 // Sum of the step terms over [m0, m1) in form kTier (not the edge form).
-template <bool kLinear, int kTier, int kUnroll, class Src>
-__device__ inline void accumulate_range32(const Term32& q, const StepLds* __restrict__ st, const Col4* __restrict__ col,
+template <bool kLinear, int kTier, int kUnroll, class Src, class SP>
+__device__ inline void accumulate_range32(const Term32& q, SP st, const Col4* __restrict__ col,
                                           const Src& src, int m0, int m1, float* a, float* b) {
   float x = 0.0f, y = 0.0f;
 #pragma unroll kUnroll
@@ -791,8 +814,8 @@ __device__ inline void accumulate_range32(const Term32& q, const StepLds* __rest
 }
 
 // S of one node: the wave's ranges in order, the edge range scaled by 1 / (2 pi phr) at the end.
-template <bool kLinear, int kUnroll, class Src>
-__device__ inline void accumulate32(const Term32& q, const Split32& sp, const StepLds* __restrict__ st,
+template <bool kLinear, int kUnroll, class Src, class SP>
+__device__ inline void accumulate32(const Term32& q, const Split32& sp, SP st,
                                     const Col4* __restrict__ col, const Src& src, int M, float* sr, float* si) {
   float a = 0.0f, b = 0.0f;
   if (sp.small) {

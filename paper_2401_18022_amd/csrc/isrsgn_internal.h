@@ -53,6 +53,7 @@ struct Work {
   double* zm;       // [n_batch * M] step midpoints
   double* dz;       // [n_batch * M] step widths
   float* hdz32;     // [n_batch * M] half widths in FP32
+  double* step_rec; // [n_batch * M] step records (StepRec, 32 bytes each)
   double* ell64;    // [M * n_total] ln rho(z_m, f_c): plan b block at M * off[b], row-major [m][c]
   float2* lt32;     // same layout: (ell * log2(e)/2, next - this) for the FP32 integrand
   // low-rank form of lt32's values (ODE profile, FP32 form): lr_a [n_batch][M][kRank] (FP32),

@@ -70,6 +70,8 @@ __global__ void k_steps(PlanView pv, FibreParams fp, const double* __restrict__ 
     w.zm[b * M + m] = 0.5 * (z0 + z1);
     w.dz[b * M + m] = z1 - z0;
     w.hdz32[b * M + m] = (float)(0.5 * (z1 - z0));
+    reinterpret_cast<StepRec*>(w.step_rec)[b * M + m] =
+        step_record(0.5 * (z0 + z1), z1 - z0, (float)(0.5 * (z1 - z0)));
   }
 }
 
@@ -311,7 +313,7 @@ struct TileArgs {
 
 // lowrank: room for the tile's terms of the low-rank exponent (FP32 form with the ODE profile only)
 __host__ __device__ inline size_t tile_lds_bytes(int nmax, int gs, int M, bool lowrank) {
-  return sizeof(double) * (3 * (size_t)nmax + 4 * (size_t)gs + 4) + (sizeof(StepLds) + sizeof(Col4)) * (size_t)M +
+  return sizeof(double) * (3 * (size_t)nmax + 4 * (size_t)gs + 4) + (sizeof(StepRec) + sizeof(Col4)) * (size_t)M +
          (lowrank ? sizeof(float) * kLrTileFloats : 0) + 16;
 }
 
@@ -343,7 +345,7 @@ k_tiles(TileArgs A) {
   d += 4 * GS;
   double* red = d;
   d += 4;
-  StepLds* steps = reinterpret_cast<StepLds*>(d);
+  StepRec* steps = reinterpret_cast<StepRec*>(d);
   Col4* col = reinterpret_cast<Col4*>(steps + M);
   float* lr_t = reinterpret_cast<float*>(col + M);  // the tile's low-rank terms (lowrank_tile_terms)
   unsigned int* tile_slot = reinterpret_cast<unsigned int*>(lr_t + (kPrec == 0 && !kLinear ? kLrTileFloats : 0));
@@ -371,7 +373,8 @@ k_tiles(TileArgs A) {
       if (kPrec == 0 && !kLinear) cur_lr = __builtin_amdgcn_readfirstlane(A.w.lr_rank[b]);
       cur_b = b;
     }
-    if (kPrec == 0) load_cols<kLinear>(col, A.w.lt32 + (size_t)M * o, n, M, sf, tf, k);
+    // (the low-rank exponent has every profile term: no table columns)
+    if (kPrec == 0 && (kLinear || cur_lr < 0)) load_cols<kLinear>(col, A.w.lt32 + (size_t)M * o, n, M, sf, tf, k);
     // FP64 form: the f-term column in the step-table slot (unused by that form)
     double* lf64 = reinterpret_cast<double*>(steps);
     if (kPrec == 1 && !kLinear) load_fcol64(lf64, A.w.ell64 + (size_t)M * o, n, M, sf, tf);
