@@ -38,13 +38,14 @@ FLOP_EQ_PER_SLOT = 2            # one FMA slot = 2 FLOP at the FP32 vector peak
 PEAK_FP32_TFLOPS = 157.3        # MI355X FP32 vector (no matrix cores)
 
 # HBM traffic per launch of the dominant kernels comes from rocprofv3 FETCH_SIZE / WRITE_SIZE
-# runs recorded in profiles/; it is reported only while the kernel's sources are unchanged.
+# runs recorded in profiles/; it is reported only while the kernel's sources and build flags
+# (build.py) are unchanged.
 CSRC = os.path.join(ROOT, "paper_2401_18022_amd", "csrc")
 TRAFFIC_RECORDS = {
     "pair_integral_forward": ("pair_integral_forward_ou589_g128_fp32.md",
-                              ["isrsgn_kernels.hip", "isrsgn_device.h", "isrsgn_internal.h"]),
+                              ["isrsgn_kernels.hip", "isrsgn_device.h", "isrsgn_internal.h", "../build.py"]),
     "pair_integral_adjoint": ("pair_integral_adjoint_ou589_g128_fp32.md",
-                              ["isrsgn_adjoint.hip", "isrsgn_device.h", "isrsgn_internal.h"]),
+                              ["isrsgn_adjoint.hip", "isrsgn_device.h", "isrsgn_internal.h", "../build.py"]),
 }
 
 
